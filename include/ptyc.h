@@ -1,0 +1,187 @@
+/*
+ * ptyc — live ePIE ptychographic reconstruction on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the shared library libptyc.so.  Plain pointers and sizes only.
+ *
+ * The method is ePIE (extended ptychographical iterative engine, Maiden &
+ * Rodenburg 2009) as used by the paper "Live Iterative Ptychography"
+ * (Weber et al. 2023), section "ePIE Implementation": for every scan
+ * position j, taken in a randomly shuffled order each iteration,
+ *
+ *   psi   = P * S_j O                       exit wave (S_j O: N x N window)
+ *   Psi   = F psi                           unnormalised 2D DFT
+ *   Psi'  = sqrt(I_j) * sgn(Psi)            modulus replacement, sgn(0) = 0
+ *   psi'  = F^-1 Psi'                       (includes 1/N^2)
+ *   S_j O += alpha conj(P) (psi' - psi) / max|P|^2
+ *   P     += beta conj(S_j O) (psi' - psi) / max|S_j O|^2
+ *
+ * with both right-hand sides taken before the update, max|P|^2 over the whole
+ * probe and max|S_j O|^2 over the position's window.  The section "Extensions
+ * of the ePIE implementation" asks that diffraction patterns can be added
+ * while the reconstruction runs and that it can be stopped, continued and
+ * read out; the Discussion asks for import and export of object, probe and
+ * data through an API and a geometry fixed in advance.  This interface
+ * provides exactly that: init (fixed geometry), add_positions (data grows),
+ * sweep (step the iteration), get/set of object and probe.
+ *
+ * Coloured mode.  Positions are grouped into batches whose N x N windows are
+ * pairwise disjoint.  All positions of batch b are updated from the same
+ * probe P_b (their object steps touch disjoint pixels and commute), and the
+ * probe then moves by the batch mean of the increments:
+ *   P_{b+1} = P_b + (beta / |B_b|) sum_{j in B_b} conj(S_j O) Delta_j / max|S_j O|^2.
+ * A batch of one position is exactly the sequential update above.  Strict
+ * mode runs every position as its own batch.
+ *
+ * Conventions
+ *   - complex data are interleaved float32 pairs (re, im), row-major,
+ *     i.e. the layout of torch.complex64 / numpy complex64.
+ *   - positions are int32 pairs (row, col): the top-left corner of the
+ *     position's N x N window in the object; 0 <= row <= H-N, 0 <= col <= W-N.
+ *   - DFT sign convention exp(-2 pi i k.r / N) forward, DC at [0, 0]; the
+ *     intensities are stored unshifted (or pass PTYC_I_CENTERED).
+ *   - mem_kind PTYC_MEM_HOST: pointer to host memory; PTYC_MEM_DEVICE:
+ *     pointer to device memory on the context's device.  The library copies
+ *     every input; the caller keeps ownership of its buffers.
+ *   - all device work is enqueued on the stream given at init (a hipStream_t,
+ *     NULL for the default stream).  get_* and sweep with err_out
+ *     synchronise that stream; nothing else blocks except add_positions,
+ *     which waits for its own validation.
+ *   - a context is used from one thread at a time.
+ *
+ * Errors: every call returns PTYC_OK (0) or a negative status.  Argument
+ * errors are detected on the host before any device work and leave the
+ * context unchanged.  After PTYC_ERR_HIP the context is poisoned: every call
+ * except ptyc_destroy and ptyc_last_error returns PTYC_ERR_STATE.  Recovery
+ * is destroy + init from the last get_object/get_probe + re-adding the data.
+ */
+#ifndef PTYC_H
+#define PTYC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PTYC_OK 0
+#define PTYC_ERR_ARG (-1)         /* invalid argument (null, size, non-power-of-two, overlap) */
+#define PTYC_ERR_BOUNDS (-2)      /* a window would leave the object */
+#define PTYC_ERR_OOM (-3)         /* device or pinned host allocation failed */
+#define PTYC_ERR_HIP (-4)         /* a HIP runtime call failed; context poisoned */
+#define PTYC_ERR_STATE (-5)       /* context poisoned by an earlier PTYC_ERR_HIP */
+
+#define PTYC_MEM_HOST 0
+#define PTYC_MEM_DEVICE 1
+
+#define PTYC_MODE_STRICT 0        /* one position per batch: sequential ePIE */
+#define PTYC_MODE_COLOURED 1      /* disjoint-window batches, batch-mean probe step */
+
+#define PTYC_I_IS_SQRT 1u         /* add_positions receives sqrt(I) instead of I */
+#define PTYC_I_CENTERED 2u        /* patterns arrive with DC at (N/2, N/2); shifted at ingest */
+
+typedef struct ptyc_config {
+    int32_t n;          /* pattern and probe side N: a power of two in [16, 256] */
+    int32_t h, w;       /* object rows and columns, each >= n and <= 65536 */
+    float alpha, beta;  /* object and probe update strengths (the paper uses 1, 1) */
+    int32_t mode;       /* PTYC_MODE_STRICT or PTYC_MODE_COLOURED */
+    int32_t max_batch;  /* coloured mode: cap on positions per batch; 0 means 1024 */
+    uint64_t seed;      /* seeds the library's own per-sweep shuffle (order == NULL) */
+    uint32_t flags;     /* PTYC_I_* bits */
+    int32_t reserved;   /* must be 0 */
+} ptyc_config;
+
+typedef struct ptyc_ctx ptyc_ctx;
+
+/* Create a context on the current HIP device with the geometry of cfg
+ * (fixed for the context's life, as the paper fixes object size and the
+ * pixel relation at initialisation, section "Determine parameters").
+ * probe0: N*N complex64, object0: H*W complex64, both in mem_kind memory,
+ * copied.  hip_stream: a hipStream_t or NULL.  On success *out receives the
+ * context.  Errors: PTYC_ERR_ARG (null pointer, N not a power of two in
+ * [16, 256], H or W < N or > 65536, bad mode/mem_kind, reserved != 0,
+ * alpha/beta not finite), PTYC_ERR_OOM, PTYC_ERR_HIP (no usable device). */
+int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0,
+              const void* object0, int mem_kind, void* hip_stream);
+
+/* Append `count` scan positions (indices n_loaded .. n_loaded+count-1, in
+ * the given order) with their diffraction intensities, while the
+ * reconstruction continues ("Extensions of the ePIE implementation").
+ * pos_yx: count*2 int32 (row, col) window corners; intensities:
+ * count*N*N float32 (photon counts, or sqrt when PTYC_I_IS_SQRT), both in
+ * mem_kind memory.  All or nothing: PTYC_ERR_BOUNDS if a window leaves the
+ * object, PTYC_ERR_ARG if an intensity is negative or not finite; then
+ * nothing is appended.  count == 0 is a no-op.  Extends the coloured
+ * schedule incrementally (greedy first-fit, earlier batches unchanged). */
+int ptyc_add_positions(ptyc_ctx* ctx, int64_t count, const int32_t* pos_yx,
+                       const float* intensities, int mem_kind);
+
+/* Run n_sweeps passes (iterations) over the loaded positions.
+ * order == NULL: the library's schedule; each sweep draws a fresh random
+ *   order from (seed, sweep counter) — strict mode: a permutation of all
+ *   positions; coloured mode: the colour batches in shuffled order,
+ *   ascending indices inside a batch.  ptyc_get_schedule exports it.
+ * order != NULL: host array of order_len position indices (each < n_loaded)
+ *   used for every sweep.  In coloured mode batch_offsets (host, n_batches+1
+ *   entries, 0 = first, last = order_len, non-decreasing) splits order into
+ *   batches, each of which must hold pairwise disjoint windows (checked on
+ *   the host, PTYC_ERR_ARG otherwise); in strict mode batch_offsets must be
+ *   NULL.
+ * err_out: NULL or n_sweeps doubles receiving the running Fourier error
+ *   sum_j sum_k (|Psi_j| - sqrt I_j)^2 / sum_j sum_k I_j of each sweep
+ *   (this synchronises the stream).  With no positions loaded a sweep is a
+ *   no-op (error 0). */
+int ptyc_sweep(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
+               int64_t order_len, const int64_t* batch_offsets,
+               int64_t n_batches, double* err_out);
+
+/* Export the schedule the next sweep with order == NULL would run:
+ * order receives n_loaded indices, batch_offsets n_batches+1 offsets (host
+ * arrays with room for n_loaded and n_loaded+1 entries; either may be NULL
+ * to query n_batches only). */
+int ptyc_get_schedule(ptyc_ctx* ctx, int64_t* order, int64_t* batch_offsets,
+                      int64_t* n_batches);
+
+/* Copy the object (H*W complex64) / probe (N*N complex64) out to, or in
+ * from, mem_kind memory.  get_* synchronise the stream. */
+int ptyc_get_object(ptyc_ctx* ctx, void* out, int mem_kind);
+int ptyc_get_probe(ptyc_ctx* ctx, void* out, int mem_kind);
+int ptyc_set_object(ptyc_ctx* ctx, const void* in, int mem_kind);
+int ptyc_set_probe(ptyc_ctx* ctx, const void* in, int mem_kind);
+
+/* Number of loaded positions (-1 for a NULL context). */
+int64_t ptyc_num_positions(const ptyc_ctx* ctx);
+/* Number of completed sweeps (drives the default shuffle). */
+int64_t ptyc_sweep_count(const ptyc_ctx* ctx);
+/* Wait for all work enqueued by this context. */
+int ptyc_synchronize(ptyc_ctx* ctx);
+/* Release the context and its device memory (NULL is a no-op). */
+void ptyc_destroy(ptyc_ctx* ctx);
+/* Text of the last error on this context (never NULL). */
+const char* ptyc_last_error(const ptyc_ctx* ctx);
+/* Text of the last error of a failed ptyc_init on this thread. */
+const char* ptyc_init_error(void);
+
+/* ---- host-only helpers (no device needed) ---- */
+
+/* Greedy first-fit colouring of window corners in index order: position j
+ * joins the lowest colour that has fewer than max_batch members and no
+ * window overlapping j's (two N x N windows overlap when |dy| < N and
+ * |dx| < N).  colour_out: count int32.  *n_colours receives the count. */
+int ptyc_colour(int64_t count, const int32_t* pos_yx, int32_t n,
+                int32_t max_batch, int32_t* colour_out, int32_t* n_colours);
+
+/* Check a batch schedule against window corners: offsets span the order,
+ * indices are < count, windows inside each batch are pairwise disjoint.
+ * Returns PTYC_OK or PTYC_ERR_ARG. */
+int ptyc_check_batches(int64_t count, const int32_t* pos_yx, int32_t n,
+                       const int64_t* order, int64_t order_len,
+                       const int64_t* batch_offsets, int64_t n_batches);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int ptyc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTYC_H */

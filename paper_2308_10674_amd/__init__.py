@@ -1,0 +1,9 @@
+"""Live ePIE ptychography on AMD Instinct MI355X (gfx950).
+
+The reconstruction runs in libptyc.so (hand-written HIP kernels behind a
+C ABI, include/ptyc.h); this package is its thin Python binding.
+"""
+from ._lib import PtycError, lib  # noqa: F401
+from .engine import Engine, check_batches, colour, current_stream_handle  # noqa: F401
+
+__all__ = ["Engine", "PtycError", "colour", "check_batches", "lib", "current_stream_handle"]

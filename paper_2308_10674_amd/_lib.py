@@ -1,0 +1,85 @@
+"""ctypes declarations of libptyc.so (the C ABI in include/ptyc.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libptyc.so")
+
+PTYC_OK = 0
+PTYC_ERR_ARG = -1
+PTYC_ERR_BOUNDS = -2
+PTYC_ERR_OOM = -3
+PTYC_ERR_HIP = -4
+PTYC_ERR_STATE = -5
+PTYC_MEM_HOST = 0
+PTYC_MEM_DEVICE = 1
+PTYC_MODE_STRICT = 0
+PTYC_MODE_COLOURED = 1
+PTYC_I_IS_SQRT = 1
+PTYC_I_CENTERED = 2
+
+STATUS_NAMES = {
+    PTYC_ERR_ARG: "PTYC_ERR_ARG", PTYC_ERR_BOUNDS: "PTYC_ERR_BOUNDS", PTYC_ERR_OOM: "PTYC_ERR_OOM",
+    PTYC_ERR_HIP: "PTYC_ERR_HIP", PTYC_ERR_STATE: "PTYC_ERR_STATE",
+}
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
+        ("alpha", C.c_float), ("beta", C.c_float),
+        ("mode", C.c_int32), ("max_batch", C.c_int32),
+        ("seed", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
+_P = C.c_void_p
+_I64P = C.POINTER(C.c_int64)
+_I32P = C.POINTER(C.c_int32)
+_DP = C.POINTER(C.c_double)
+
+SIGNATURES = {
+    "ptyc_init": (C.c_int, [C.POINTER(_P), C.POINTER(Config), _P, _P, C.c_int, _P]),
+    "ptyc_add_positions": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int]),
+    "ptyc_sweep": (C.c_int, [_P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64, _DP]),
+    "ptyc_get_schedule": (C.c_int, [_P, _I64P, _I64P, _I64P]),
+    "ptyc_get_object": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_get_probe": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_set_object": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_set_probe": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_num_positions": (C.c_int64, [_P]),
+    "ptyc_sweep_count": (C.c_int64, [_P]),
+    "ptyc_synchronize": (C.c_int, [_P]),
+    "ptyc_destroy": (None, [_P]),
+    "ptyc_last_error": (C.c_char_p, [_P]),
+    "ptyc_init_error": (C.c_char_p, []),
+    "ptyc_colour": (C.c_int, [C.c_int64, _P, C.c_int32, C.c_int32, _I32P, _I32P]),
+    "ptyc_check_batches": (C.c_int, [C.c_int64, _P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64]),
+    "ptyc_version": (C.c_int, []),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2308_10674_amd.build.build() "
+                              "(there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PtycError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status

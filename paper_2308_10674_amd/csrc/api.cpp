@@ -1,0 +1,536 @@
+// C ABI of libptyc: context, ingest, schedule and sweep orchestration.
+// Declarations and the contract of every call are in include/ptyc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ptyc.h"
+#include "kernels.h"
+#include "schedule.h"
+
+using namespace ptyc;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ptyc_ctx {
+    ptyc_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool poisoned = false;
+    std::string err;
+    Shape shape{};
+
+    // device state
+    DevBuf obj, probe, tw;
+    DevBuf sqrt_i, pos, sum_i;       // per position, capacity cap
+    int64_t cap = 0, n_loaded = 0;
+    DevBuf scratch, dprobe, winmax;  // per batch slot, capacity slots
+    int64_t slots = 0;
+    DevBuf pmax_part;
+    DevBuf order;                    // int64 [order_cap]
+    DevBuf err_part, err_dev;
+    DevBuf bad;                      // int flag for ingest validation
+    DevBuf staging;                  // host intensities staged on the device
+
+    // host state
+    std::vector<int32_t> h_pos;      // 2 per position
+    Colouring* colouring = nullptr;
+    int64_t sweeps_done = 0;
+    int64_t* pinned_order = nullptr; // pinned upload buffer
+    size_t pinned_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+
+    size_t dev_bytes = 0, dev_limit = 0;
+};
+
+namespace {
+
+int fail(ptyc_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(ptyc_ctx* c, hipError_t e, const char* what) {
+    c->poisoned = true;
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return PTYC_ERR_HIP;
+}
+
+#define HIPCHK(c, expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
+    } while (0)
+
+size_t env_limit() {
+    const char* s = std::getenv("PTYC_MAX_DEVICE_BYTES");
+    if (!s || !*s) return 0;
+    return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+// (re)allocate a device buffer to at least `bytes`, keeping `keep` bytes of content
+int ensure(ptyc_ctx* c, DevBuf& b, size_t bytes, size_t keep = 0) {
+    if (b.bytes >= bytes) return PTYC_OK;
+    size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+    if (c->dev_limit && c->dev_bytes - b.bytes + want > c->dev_limit) {
+        want = bytes;
+        if (c->dev_bytes - b.bytes + want > c->dev_limit)
+            return fail(c, PTYC_ERR_OOM, "device memory cap (PTYC_MAX_DEVICE_BYTES) exceeded");
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, PTYC_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    if (b.p) {
+        if (keep) {
+            e = hipMemcpyAsync(p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync(grow)");
+        }
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize(grow)");
+        (void)hipFree(b.p);
+        c->dev_bytes -= b.bytes;
+    }
+    b.p = p;
+    b.bytes = want;
+    c->dev_bytes += want;
+    return PTYC_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+bool valid_kind(int k) { return k == PTYC_MEM_HOST || k == PTYC_MEM_DEVICE; }
+
+hipMemcpyKind to_dev(int k) { return k == PTYC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice; }
+hipMemcpyKind from_dev(int k) { return k == PTYC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice; }
+
+int validate_config(const ptyc_config* cfg, std::string* why) {
+    if (!cfg) { *why = "cfg is NULL"; return PTYC_ERR_ARG; }
+    if (!supported_n(cfg->n)) { *why = "n must be a power of two in [16, 256]"; return PTYC_ERR_ARG; }
+    if (cfg->h < cfg->n || cfg->w < cfg->n) { *why = "object must be at least n x n"; return PTYC_ERR_ARG; }
+    if (cfg->h > 65536 || cfg->w > 65536) { *why = "object sides must be <= 65536"; return PTYC_ERR_ARG; }
+    if (cfg->mode != PTYC_MODE_STRICT && cfg->mode != PTYC_MODE_COLOURED) { *why = "unknown mode"; return PTYC_ERR_ARG; }
+    if (cfg->max_batch < 0) { *why = "max_batch must be >= 0"; return PTYC_ERR_ARG; }
+    if (!std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta)) { *why = "alpha and beta must be finite"; return PTYC_ERR_ARG; }
+    if (cfg->flags & ~(PTYC_I_IS_SQRT | PTYC_I_CENTERED)) { *why = "unknown flag bits"; return PTYC_ERR_ARG; }
+    if (cfg->reserved != 0) { *why = "reserved must be 0"; return PTYC_ERR_ARG; }
+    return PTYC_OK;
+}
+
+int usable(ptyc_ctx* c) {
+    if (!c) return PTYC_ERR_ARG;
+    if (c->poisoned) return PTYC_ERR_STATE;
+    return PTYC_OK;
+}
+
+int32_t max_batch_of(const ptyc_ctx* c) { return c->cfg.max_batch > 0 ? c->cfg.max_batch : 1024; }
+
+// the schedule the library uses for sweep number `sweep`
+void default_schedule(const ptyc_ctx* c, int64_t sweep, std::vector<int64_t>& order,
+                      std::vector<int64_t>& off) {
+    order.clear();
+    off.clear();
+    off.push_back(0);
+    if (c->cfg.mode == PTYC_MODE_STRICT) {
+        order = shuffled(c->n_loaded, c->cfg.seed, (uint64_t)sweep);
+        for (int64_t i = 1; i <= c->n_loaded; ++i) off.push_back(i);
+        return;
+    }
+    const auto& mem = c->colouring->members();
+    std::vector<int64_t> perm = shuffled((int64_t)mem.size(), c->cfg.seed, (uint64_t)sweep);
+    order.reserve((size_t)c->n_loaded);
+    for (int64_t b : perm) {
+        const auto& m = mem[(size_t)b];
+        order.insert(order.end(), m.begin(), m.end());
+        off.push_back((int64_t)order.size());
+    }
+}
+
+BatchArgs base_args(ptyc_ctx* c) {
+    BatchArgs a{};
+    a.obj = (cf*)c->obj.p;
+    a.h = c->cfg.h;
+    a.w = c->cfg.w;
+    a.probe = (cf*)c->probe.p;
+    a.tw = (const cf*)c->tw.p;
+    a.sqrt_i = (const float*)c->sqrt_i.p;
+    a.pos = (const int2*)c->pos.p;
+    a.order = (const int64_t*)c->order.p;
+    a.scratch = (cf*)c->scratch.p;
+    a.dprobe = (cf*)c->dprobe.p;
+    a.winmax = (float*)c->winmax.p;
+    a.pmax_part = (float*)c->pmax_part.p;
+    a.npmax = c->shape.probe_blocks;
+    a.err_part = (double*)c->err_part.p;
+    a.alpha = c->cfg.alpha;
+    a.beta = c->cfg.beta;
+    return a;
+}
+
+int copy_square_in(ptyc_ctx* c, DevBuf& dst, const void* src, size_t bytes, int kind) {
+    HIPCHK(c, hipMemcpyAsync(dst.p, src, bytes, to_dev(kind), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
+int refresh_probe_max(ptyc_ctx* c) {
+    BatchArgs a = base_args(c);
+    a.bsize = 0;
+    HIPCHK(c, launch_probe_reduce(c->cfg.n, a, c->stream));
+    return PTYC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ptyc_version(void) { return 100; }
+
+const char* ptyc_init_error(void) { return g_init_error.c_str(); }
+
+int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const void* object0,
+              int mem_kind, void* hip_stream) {
+    g_init_error.clear();
+    std::string why;
+    if (!out) { g_init_error = "out is NULL"; return PTYC_ERR_ARG; }
+    *out = nullptr;
+    int rc = validate_config(cfg, &why);
+    if (rc != PTYC_OK) { g_init_error = why; return rc; }
+    if (!probe0 || !object0) { g_init_error = "probe0 and object0 must not be NULL"; return PTYC_ERR_ARG; }
+    if (!valid_kind(mem_kind)) { g_init_error = "unknown mem_kind"; return PTYC_ERR_ARG; }
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        g_init_error = std::string("no HIP device: ") + hipGetErrorString(e);
+        return PTYC_ERR_HIP;
+    }
+    ptyc_ctx* c = new ptyc_ctx();
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)hip_stream;
+    c->shape = shape_for(cfg->n);
+    c->dev_limit = env_limit();
+    c->colouring = new Colouring(cfg->n, max_batch_of(c));
+    (void)hipGetDevice(&c->device);
+
+    const int n = cfg->n;
+    const size_t obj_bytes = (size_t)cfg->h * cfg->w * sizeof(cf);
+    const size_t pr_bytes = (size_t)n * n * sizeof(cf);
+    auto bail = [&](int code) {
+        g_init_error = c->err;
+        ptyc_destroy(c);
+        return code;
+    };
+    if ((rc = ensure(c, c->obj, obj_bytes)) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->probe, pr_bytes)) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->tw, n * sizeof(cf))) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->pmax_part, c->shape.probe_blocks * sizeof(float))) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->bad, sizeof(int))) != PTYC_OK) return bail(rc);
+    // twiddles exp(-2 pi i m / n) in double precision, rounded once to float
+    std::vector<cf> tw((size_t)n);
+    for (int m = 0; m < n; ++m) {
+        const double ang = -2.0 * M_PI * (double)m / (double)n;
+        tw[(size_t)m] = cf{(float)std::cos(ang), (float)std::sin(ang)};
+    }
+    if ((rc = copy_square_in(c, c->tw, tw.data(), n * sizeof(cf), PTYC_MEM_HOST)) != PTYC_OK) return bail(rc);
+    if ((rc = copy_square_in(c, c->obj, object0, obj_bytes, mem_kind)) != PTYC_OK) return bail(rc);
+    if ((rc = copy_square_in(c, c->probe, probe0, pr_bytes, mem_kind)) != PTYC_OK) return bail(rc);
+    if ((e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming)) != hipSuccess) {
+        hip_fail(c, e, "hipEventCreate");
+        return bail(PTYC_ERR_HIP);
+    }
+    if ((rc = refresh_probe_max(c)) != PTYC_OK) return bail(rc);
+    *out = c;
+    return PTYC_OK;
+}
+
+void ptyc_destroy(ptyc_ctx* c) {
+    if (!c) return;
+    if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
+    DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
+                      &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->err_part,
+                      &c->err_dev, &c->bad, &c->staging};
+    for (DevBuf* b : bufs) release(*b);
+    if (c->pinned_order) (void)hipHostFree(c->pinned_order);
+    if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    delete c->colouring;
+    delete c;
+}
+
+const char* ptyc_last_error(const ptyc_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int64_t ptyc_num_positions(const ptyc_ctx* c) { return c ? c->n_loaded : -1; }
+
+int64_t ptyc_sweep_count(const ptyc_ctx* c) { return c ? c->sweeps_done : -1; }
+
+int ptyc_synchronize(ptyc_ctx* c) {
+    int rc = usable(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
+int ptyc_add_positions(ptyc_ctx* c, int64_t count, const int32_t* pos_yx, const float* inten,
+                       int mem_kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (count < 0) return fail(c, PTYC_ERR_ARG, "count must be >= 0");
+    if (count == 0) return PTYC_OK;
+    if (!pos_yx || !inten) return fail(c, PTYC_ERR_ARG, "pos_yx and intensities must not be NULL");
+    if (!valid_kind(mem_kind)) return fail(c, PTYC_ERR_ARG, "unknown mem_kind");
+    const int n = c->cfg.n;
+    const size_t nn = (size_t)n * n;
+
+    // positions to the host for the bounds check and the schedule
+    std::vector<int32_t> p((size_t)(2 * count));
+    if (mem_kind == PTYC_MEM_HOST) {
+        std::memcpy(p.data(), pos_yx, p.size() * sizeof(int32_t));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(p.data(), pos_yx, p.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    for (int64_t i = 0; i < count; ++i) {
+        const int32_t y = p[(size_t)(2 * i)], x = p[(size_t)(2 * i + 1)];
+        if (y < 0 || x < 0 || y > c->cfg.h - n || x > c->cfg.w - n)
+            return fail(c, PTYC_ERR_BOUNDS, "position " + std::to_string(i) + " (" + std::to_string(y) + ", " +
+                                                std::to_string(x) + ") puts its window outside the object");
+    }
+    const int64_t first = c->n_loaded, total = first + count;
+    if (total > c->cap) {
+        int64_t ncap = std::max<int64_t>(total, std::max<int64_t>(64, c->cap * 2));
+        if ((rc = ensure(c, c->sqrt_i, (size_t)ncap * nn * sizeof(float), (size_t)first * nn * sizeof(float))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->pos, (size_t)ncap * sizeof(int2), (size_t)first * sizeof(int2))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->sum_i, (size_t)ncap * sizeof(double), (size_t)first * sizeof(double))) != PTYC_OK) return rc;
+        c->cap = ncap;
+    }
+    HIPCHK(c, hipMemsetAsync(c->bad.p, 0, sizeof(int), c->stream));
+    const bool is_sqrt = (c->cfg.flags & PTYC_I_IS_SQRT) != 0;
+    const bool centred = (c->cfg.flags & PTYC_I_CENTERED) != 0;
+    float* dst = (float*)c->sqrt_i.p + (size_t)first * nn;
+    double* sdst = (double*)c->sum_i.p + first;
+    if (mem_kind == PTYC_MEM_DEVICE) {
+        HIPCHK(c, launch_ingest(n, inten, dst, sdst, count, is_sqrt, centred, (int*)c->bad.p, c->stream));
+    } else {
+        // stage through a bounded device buffer
+        const int64_t chunk = std::max<int64_t>(1, (int64_t)((size_t)(64u << 20) / (nn * sizeof(float))));
+        const int64_t cn = std::min(chunk, count);
+        if ((rc = ensure(c, c->staging, (size_t)cn * nn * sizeof(float))) != PTYC_OK) return rc;
+        for (int64_t a = 0; a < count; a += cn) {
+            const int64_t m = std::min(cn, count - a);
+            HIPCHK(c, hipMemcpyAsync(c->staging.p, inten + (size_t)a * nn, (size_t)m * nn * sizeof(float),
+                                     hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, launch_ingest(n, (const float*)c->staging.p, dst + (size_t)a * nn, sdst + a, m, is_sqrt,
+                                    centred, (int*)c->bad.p, c->stream));
+        }
+    }
+    std::vector<int2> pd((size_t)count);
+    for (int64_t i = 0; i < count; ++i) pd[(size_t)i] = make_int2(p[(size_t)(2 * i)], p[(size_t)(2 * i + 1)]);
+    HIPCHK(c, hipMemcpyAsync((int2*)c->pos.p + first, pd.data(), (size_t)count * sizeof(int2),
+                             hipMemcpyHostToDevice, c->stream));
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, PTYC_ERR_ARG, "intensities must be finite and >= 0");
+    c->h_pos.insert(c->h_pos.end(), p.begin(), p.end());
+    c->colouring->extend(c->h_pos.data(), first, count);
+    c->n_loaded = total;
+    return PTYC_OK;
+}
+
+int ptyc_get_schedule(ptyc_ctx* c, int64_t* order, int64_t* off, int64_t* n_batches) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!n_batches) return fail(c, PTYC_ERR_ARG, "n_batches must not be NULL");
+    std::vector<int64_t> o, f;
+    default_schedule(c, c->sweeps_done, o, f);
+    *n_batches = (int64_t)f.size() - 1;
+    if (order) std::memcpy(order, o.data(), o.size() * sizeof(int64_t));
+    if (off) std::memcpy(off, f.data(), f.size() * sizeof(int64_t));
+    return PTYC_OK;
+}
+
+int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t order_len,
+               const int64_t* off, int64_t n_batches, double* err_out) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (n_sweeps < 0) return fail(c, PTYC_ERR_ARG, "n_sweeps must be >= 0");
+    if (n_sweeps == 0) return PTYC_OK;
+    std::string why;
+    const bool strict = c->cfg.mode == PTYC_MODE_STRICT;
+    if (order) {
+        if (order_len < 0) return fail(c, PTYC_ERR_ARG, "order_len must be >= 0");
+        if (strict && off) return fail(c, PTYC_ERR_ARG, "strict mode takes no batch_offsets");
+        if (!strict && !off) return fail(c, PTYC_ERR_ARG, "coloured mode needs batch_offsets with an explicit order");
+        if (!strict) {
+            if (n_batches < 0) return fail(c, PTYC_ERR_ARG, "n_batches must be >= 0");
+            if (!check_batches(c->n_loaded, c->h_pos.data(), c->cfg.n, order, order_len, off, n_batches, &why))
+                return fail(c, PTYC_ERR_ARG, why);
+        } else {
+            for (int64_t i = 0; i < order_len; ++i)
+                if (order[i] < 0 || order[i] >= c->n_loaded)
+                    return fail(c, PTYC_ERR_ARG, "order index " + std::to_string(order[i]) + " is not a loaded position");
+        }
+    }
+    if (c->n_loaded == 0 || (order && order_len == 0)) {
+        if (err_out)
+            for (int s = 0; s < n_sweeps; ++s) err_out[s] = 0.0;
+        c->sweeps_done += n_sweeps;
+        return PTYC_OK;
+    }
+
+    // host schedules of all sweeps
+    std::vector<std::vector<int64_t>> orders((size_t)n_sweeps), offs((size_t)n_sweeps);
+    for (int s = 0; s < n_sweeps; ++s) {
+        if (order) {
+            orders[(size_t)s].assign(order, order + order_len);
+            if (strict) {
+                offs[(size_t)s].resize((size_t)order_len + 1);
+                for (int64_t i = 0; i <= order_len; ++i) offs[(size_t)s][(size_t)i] = i;
+            } else {
+                offs[(size_t)s].assign(off, off + n_batches + 1);
+            }
+        } else {
+            default_schedule(c, c->sweeps_done + s, orders[(size_t)s], offs[(size_t)s]);
+        }
+    }
+    const int64_t olen = (int64_t)orders[0].size();
+    int64_t max_b = 1;
+    for (int s = 0; s < n_sweeps; ++s)
+        for (size_t b = 0; b + 1 < offs[(size_t)s].size(); ++b)
+            max_b = std::max(max_b, offs[(size_t)s][b + 1] - offs[(size_t)s][b]);
+
+    // buffers
+    const size_t nn = (size_t)c->cfg.n * c->cfg.n;
+    if (max_b > c->slots) {
+        if ((rc = ensure(c, c->scratch, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->dprobe, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->winmax, (size_t)max_b * c->shape.row_blocks * sizeof(float))) != PTYC_OK) return rc;
+        c->slots = max_b;
+    }
+    const size_t obytes = (size_t)n_sweeps * olen * sizeof(int64_t);
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    if ((rc = ensure(c, c->order, obytes)) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_part, (size_t)olen * c->shape.col_blocks * sizeof(double))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_dev, (size_t)n_sweeps * sizeof(double))) != PTYC_OK) return rc;
+    if (c->pinned_bytes < obytes) {
+        if (c->pinned_order) (void)hipHostFree(c->pinned_order);
+        c->pinned_order = nullptr;
+        c->pinned_bytes = 0;
+        hipError_t e = hipHostMalloc((void**)&c->pinned_order, obytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, PTYC_ERR_OOM, "pinned host allocation failed");
+        }
+        c->pinned_bytes = obytes;
+    }
+    for (int s = 0; s < n_sweeps; ++s)
+        std::memcpy(c->pinned_order + (size_t)s * olen, orders[(size_t)s].data(), (size_t)olen * sizeof(int64_t));
+    HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, obytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
+    c->upload_pending = true;
+
+    if ((rc = refresh_probe_max(c)) != PTYC_OK) return rc;
+    for (int s = 0; s < n_sweeps; ++s) {
+        BatchArgs a = base_args(c);
+        a.order = (const int64_t*)c->order.p + (size_t)s * olen;
+        const auto& f = offs[(size_t)s];
+        for (size_t b = 0; b + 1 < f.size(); ++b) {
+            a.off = f[b];
+            a.bsize = (int)(f[b + 1] - f[b]);
+            if (a.bsize == 0) continue;
+            HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
+        }
+        if (err_out)
+            HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, olen * c->shape.col_blocks, a.order, olen,
+                                        (const double*)c->sum_i.p, (double*)c->err_dev.p + s, c->stream));
+    }
+    c->sweeps_done += n_sweeps;
+    if (err_out) {
+        HIPCHK(c, hipMemcpyAsync(err_out, c->err_dev.p, (size_t)n_sweeps * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return PTYC_OK;
+}
+
+int ptyc_get_object(ptyc_ctx* c, void* out, int kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!out || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad output buffer or mem_kind");
+    HIPCHK(c, hipMemcpyAsync(out, c->obj.p, (size_t)c->cfg.h * c->cfg.w * sizeof(cf), from_dev(kind), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
+int ptyc_get_probe(ptyc_ctx* c, void* out, int kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!out || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad output buffer or mem_kind");
+    HIPCHK(c, hipMemcpyAsync(out, c->probe.p, (size_t)c->cfg.n * c->cfg.n * sizeof(cf), from_dev(kind), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
+int ptyc_set_object(ptyc_ctx* c, const void* in, int kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!in || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad input buffer or mem_kind");
+    return copy_square_in(c, c->obj, in, (size_t)c->cfg.h * c->cfg.w * sizeof(cf), kind);
+}
+
+int ptyc_set_probe(ptyc_ctx* c, const void* in, int kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!in || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad input buffer or mem_kind");
+    if ((rc = copy_square_in(c, c->probe, in, (size_t)c->cfg.n * c->cfg.n * sizeof(cf), kind)) != PTYC_OK) return rc;
+    return refresh_probe_max(c);
+}
+
+int ptyc_colour(int64_t count, const int32_t* pos_yx, int32_t n, int32_t max_batch, int32_t* colour_out,
+                int32_t* n_colours) {
+    if (count < 0 || n <= 0 || max_batch < 0 || (count > 0 && (!pos_yx || !colour_out)) || !n_colours)
+        return PTYC_ERR_ARG;
+    for (int64_t i = 0; i < 2 * count; ++i)
+        if (pos_yx[i] < 0) return PTYC_ERR_BOUNDS;
+    Colouring col(n, max_batch > 0 ? max_batch : 1024);
+    col.extend(pos_yx, 0, count);
+    for (int64_t i = 0; i < count; ++i) colour_out[i] = col.colour()[(size_t)i];
+    *n_colours = (int32_t)col.members().size();
+    return PTYC_OK;
+}
+
+int ptyc_check_batches(int64_t count, const int32_t* pos_yx, int32_t n, const int64_t* order, int64_t order_len,
+                       const int64_t* off, int64_t n_batches) {
+    if (count < 0 || n <= 0 || order_len < 0 || n_batches < 0 || !off || (order_len > 0 && !order) ||
+        (count > 0 && !pos_yx))
+        return PTYC_ERR_ARG;
+    std::string why;
+    return check_batches(count, pos_yx, n, order, order_len, off, n_batches, &why) ? PTYC_OK : PTYC_ERR_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// Complex FP32 arithmetic and small in-register DFTs for the ePIE kernels.
+//
+// A length-N transform (N = N1 * N2) is computed by the four-step
+// factorisation: with n = N2*n1 + n2 and k = k1 + N1*k2,
+//   X[k1 + N1 k2] = sum_n2 W_N2^(n2 k2) W_N^(n2 k1) sum_n1 x[N2 n1 + n2] W_N1^(n1 k1)
+// so a group of N2 threads first runs N2 DFTs of length N1 in registers
+// (pass A), multiplies by W_N^(n2 k1), exchanges through LDS and runs N1
+// DFTs of length N2 (pass B).  The inverse runs the same passes backwards
+// (B^-1 then A^-1) and ends in the distribution the forward pass started
+// from.  The small DFTs below use exact mathematical constants; the N-point
+// twiddles come from a table computed in double precision on the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ptyc {
+
+struct __align__(8) cf {
+    float x, y;
+};
+
+__host__ __device__ inline cf mk(float x, float y) { return cf{x, y}; }
+__host__ __device__ inline cf operator+(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cf operator-(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cf operator*(float s, cf a) { return cf{s * a.x, s * a.y}; }
+__host__ __device__ inline cf cmul(cf a, cf b) {
+    return cf{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// conj(a) * b
+__host__ __device__ inline cf cmulc(cf a, cf b) {
+    return cf{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ inline float norm2(cf a) { return a.x * a.x + a.y * a.y; }
+
+// multiply by DIR*i (DIR = -1 forward, +1 inverse): W_4^1 of that direction
+template <int DIR>
+__host__ __device__ inline cf rot(cf v) {
+    return DIR < 0 ? cf{v.y, -v.x} : cf{-v.y, v.x};
+}
+
+// multiply by the constant (c + DIR*i*s)
+template <int DIR>
+__host__ __device__ inline cf twc(cf v, float c, float s) {
+    const float sd = DIR < 0 ? -s : s;
+    return cf{v.x * c - v.y * sd, v.x * sd + v.y * c};
+}
+
+// cos and sin of pi/8 and pi/4 (mathematical constants)
+constexpr float kC8 = 0.92387953251128675613f;   // cos(pi/8)
+constexpr float kS8 = 0.38268343236508977173f;   // sin(pi/8)
+constexpr float kR2 = 0.70710678118654752440f;   // cos(pi/4) = sin(pi/4)
+
+template <int DIR>
+__host__ __device__ inline void dft2(cf& a, cf& b) {
+    cf t = a - b;
+    a = a + b;
+    b = t;
+}
+
+// v[0..3] -> natural-order DFT of length 4
+template <int DIR>
+__host__ __device__ inline void dft4(cf& v0, cf& v1, cf& v2, cf& v3) {
+    cf t0 = v0 + v2, t1 = v0 - v2, t2 = v1 + v3, t3 = rot<DIR>(v1 - v3);
+    v0 = t0 + t2;
+    v2 = t0 - t2;
+    v1 = t1 + t3;
+    v3 = t1 - t3;
+}
+
+// natural-order DFT of length 8 (radix-2 split of two length-4 DFTs)
+template <int DIR>
+__host__ __device__ inline void dft8(cf* v) {
+    cf e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cf o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    o1 = twc<DIR>(o1, kR2, kR2);       // W_8^1
+    o2 = rot<DIR>(o2);                 // W_8^2
+    o3 = twc<DIR>(o3, -kR2, kR2);      // W_8^3
+    v[0] = e0 + o0; v[4] = e0 - o0;
+    v[1] = e1 + o1; v[5] = e1 - o1;
+    v[2] = e2 + o2; v[6] = e2 - o2;
+    v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+// natural-order DFT of length 16 (four-step 4 x 4)
+template <int DIR>
+__host__ __device__ inline void dft16(cf* v) {
+    cf y[16];
+    // DFTs of length 4 over n1 for each n2: inputs x[4 n1 + n2]
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        cf a = v[n2], b = v[4 + n2], c = v[8 + n2], d = v[12 + n2];
+        dft4<DIR>(a, b, c, d);
+        y[0 * 4 + n2] = a;   // y[k1*4 + n2]
+        y[1 * 4 + n2] = b;
+        y[2 * 4 + n2] = c;
+        y[3 * 4 + n2] = d;
+    }
+    // twiddles W_16^(n2 k1)
+    y[1 * 4 + 1] = twc<DIR>(y[1 * 4 + 1], kC8, kS8);    // m = 1
+    y[1 * 4 + 2] = twc<DIR>(y[1 * 4 + 2], kR2, kR2);    // m = 2
+    y[1 * 4 + 3] = twc<DIR>(y[1 * 4 + 3], kS8, kC8);    // m = 3
+    y[2 * 4 + 1] = twc<DIR>(y[2 * 4 + 1], kR2, kR2);    // m = 2
+    y[2 * 4 + 2] = rot<DIR>(y[2 * 4 + 2]);              // m = 4
+    y[2 * 4 + 3] = twc<DIR>(y[2 * 4 + 3], -kR2, kR2);   // m = 6
+    y[3 * 4 + 1] = twc<DIR>(y[3 * 4 + 1], kS8, kC8);    // m = 3
+    y[3 * 4 + 2] = twc<DIR>(y[3 * 4 + 2], -kR2, kR2);   // m = 6
+    y[3 * 4 + 3] = twc<DIR>(y[3 * 4 + 3], -kC8, -kS8);  // m = 9
+    // DFTs of length 4 over n2 for each k1: output X[k1 + 4 k2]
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cf a = y[k1 * 4 + 0], b = y[k1 * 4 + 1], c = y[k1 * 4 + 2], d = y[k1 * 4 + 3];
+        dft4<DIR>(a, b, c, d);
+        v[k1 + 0] = a;
+        v[k1 + 4] = b;
+        v[k1 + 8] = c;
+        v[k1 + 12] = d;
+    }
+}
+
+template <int R, int DIR>
+__host__ __device__ inline void dft(cf* v) {
+    static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+    if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+    else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<DIR>(v);
+    else dft16<DIR>(v);
+}
+
+// Factorisation N = N1 * N2 used for each supported pattern size.
+// T = N2 threads cooperate on one length-N transform; each holds N1 points.
+template <int N> struct Fact;
+template <> struct Fact<16>  { static constexpr int N1 = 4,  N2 = 4; };
+template <> struct Fact<32>  { static constexpr int N1 = 8,  N2 = 4; };
+template <> struct Fact<64>  { static constexpr int N1 = 8,  N2 = 8; };
+template <> struct Fact<128> { static constexpr int N1 = 16, N2 = 8; };
+template <> struct Fact<256> { static constexpr int N1 = 16, N2 = 16; };
+
+// LDS exchange buffer of one length-N line: Z[k1][n2] at k1*(N2+1) + n2,
+// padded to an odd number of complex slots per line.
+template <int N>
+struct Lds {
+    static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
+    static constexpr int RAW = N1 * (N2 + 1);
+    static constexpr int LINE = (RAW % 2 == 0) ? RAW + 1 : RAW;
+    __host__ __device__ static inline int at(int k1, int n2) { return k1 * (N2 + 1) + n2; }
+};
+
+// Pass A of a forward (DIR=-1) transform.  In: v[n1] = x[N2 n1 + t].
+// Out: Z[k1][t] = W_N^(t k1) * sum_n1 x[N2 n1 + t] W_N1^(n1 k1).
+// tw[m] = exp(-2 pi i m / N), m < N.
+template <int N, int DIR>
+__host__ __device__ inline void passA_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+    constexpr int N1 = Fact<N>::N1;
+    dft<N1, DIR>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        cf w = tw[t * k1];
+        if (DIR > 0) w.y = -w.y;
+        z[Lds<N>::at(k1, t)] = (k1 == 0) ? v[k1] : cmul(v[k1], w);
+    }
+}
+
+// Pass B.  Thread t handles k1 = t + N2 m, m < N1/N2.
+// Out: v[m N2 + k2] = X[(t + N2 m) + N1 k2].
+template <int N, int DIR>
+__host__ __device__ inline void passB_from_lds(cf* v, const cf* z, int t) {
+    constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
+#pragma unroll
+    for (int m = 0; m < N1 / N2; ++m) {
+        cf u[N2];
+        const int k1 = t + N2 * m;
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) u[n2] = z[Lds<N>::at(k1, n2)];
+        dft<N2, DIR>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) v[m * N2 + k2] = u[k2];
+    }
+}
+
+// Inverse of pass B: from v[m N2 + k2] = X[(t + N2 m) + N1 k2] to
+// Z[k1][n2] = W_N^(DIR n2 k1 ...) * sum_k2 X[k1 + N1 k2] W_N2^(n2 k2) for the
+// transform direction DIR (the conjugate of the forward direction).
+template <int N, int DIR>
+__host__ __device__ inline void passBinv_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+    constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
+#pragma unroll
+    for (int m = 0; m < N1 / N2; ++m) {
+        cf u[N2];
+        const int k1 = t + N2 * m;
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) u[k2] = v[m * N2 + k2];
+        dft<N2, DIR>(u);
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+            cf w = tw[n2 * k1];
+            if (DIR > 0) w.y = -w.y;
+            z[Lds<N>::at(k1, n2)] = cmul(u[n2], w);
+        }
+    }
+}
+
+// Inverse of pass A: thread t = n2 reads Z[k1][t], k1 < N1, and ends with
+// v[n1] = x[N2 n1 + t].
+template <int N, int DIR>
+__host__ __device__ inline void passAinv_from_lds(cf* v, const cf* z, int t) {
+    constexpr int N1 = Fact<N>::N1;
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = z[Lds<N>::at(k1, t)];
+    dft<N1, DIR>(v);
+}
+
+}  // namespace ptyc

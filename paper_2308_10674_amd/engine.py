@@ -1,0 +1,198 @@
+"""Python face of libptyc: argument marshalling onto the C ABI, nothing else.
+
+Every step of the reconstruction runs in the library's HIP kernels; torch is
+used only for device tensors (inputs and outputs that live on the GPU) and
+for the current HIP stream.  There is no CPU fallback: if libptyc.so is
+missing or no GPU is present, the calls fail.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+try:  # torch is optional for host-only use
+    import torch
+except Exception:  # pragma: no cover
+    torch = None
+
+
+def _check(rc: int, ctx=None):
+    if rc != L.PTYC_OK:
+        lib = L.lib()
+        msg = lib.ptyc_last_error(ctx).decode() if ctx else lib.ptyc_init_error().decode()
+        raise L.PtycError(rc, msg)
+
+
+def _buffer(x, np_dtype, torch_dtype):
+    """(pointer, mem_kind, keepalive) for a numpy array or torch tensor."""
+    if torch is not None and isinstance(x, torch.Tensor):
+        t = x.detach()
+        if t.dtype != torch_dtype:
+            t = t.to(torch_dtype)
+        t = t.contiguous()
+        kind = L.PTYC_MEM_DEVICE if t.is_cuda else L.PTYC_MEM_HOST
+        return t.data_ptr(), kind, t
+    a = np.ascontiguousarray(x, dtype=np_dtype)
+    return a.ctypes.data, L.PTYC_MEM_HOST, a
+
+
+def _i64(a):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def current_stream_handle():
+    """The raw hipStream_t of torch's current stream (None without a GPU)."""
+    if torch is not None and torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+class Engine:
+    """A live ePIE reconstruction (one libptyc context).
+
+    Geometry is fixed at construction; positions and patterns are appended
+    with add_positions while sweeps run.  mode "strict" is sequential ePIE,
+    "coloured" batches positions with disjoint windows.
+    """
+
+    def __init__(self, n, h, w, probe0, object0, *, alpha=1.0, beta=1.0, mode="coloured",
+                 max_batch=0, seed=0, sqrt_input=False, centred=False, stream=None):
+        lib = L.lib()
+        cfg = L.Config(n=n, h=h, w=w, alpha=alpha, beta=beta,
+                       mode=L.PTYC_MODE_STRICT if mode == "strict" else L.PTYC_MODE_COLOURED,
+                       max_batch=max_batch, seed=seed,
+                       flags=(L.PTYC_I_IS_SQRT if sqrt_input else 0) | (L.PTYC_I_CENTERED if centred else 0),
+                       reserved=0)
+        tdt = torch.complex64 if torch is not None else None
+        pp, pk, pkeep = _buffer(probe0, np.complex64, tdt)
+        op, ok, okeep = _buffer(object0, np.complex64, tdt)
+        if pk != ok:
+            raise ValueError("probe0 and object0 must both be host or both be device buffers")
+        if stream is None:
+            stream = current_stream_handle()
+        self._ctx = C.c_void_p()
+        self.n, self.h, self.w, self.mode = n, h, w, mode
+        _check(lib.ptyc_init(C.byref(self._ctx), C.byref(cfg), pp, op, pk, stream))
+
+    # ------------------------------------------------------------------ data
+    def add_positions(self, positions, intensities):
+        """positions: [count, 2] int32 window corners (row, col);
+        intensities: [count, n, n] float32 (host or device)."""
+        lib = L.lib()
+        tf = torch.float32 if torch is not None else None
+        ti = torch.int32 if torch is not None else None
+        pp, pk, pkeep = _buffer(positions, np.int32, ti)
+        ip, ik, ikeep = _buffer(intensities, np.float32, tf)
+        count = int(np.prod(pkeep.shape) // 2)
+        if pk != ik:
+            # positions are tiny: bring them to the intensities' side
+            pos_np = np.ascontiguousarray(
+                positions.cpu().numpy() if (torch is not None and isinstance(positions, torch.Tensor))
+                else positions, dtype=np.int32)
+            if ik == L.PTYC_MEM_DEVICE:
+                pkeep = torch.from_numpy(pos_np).to(ikeep.device)
+                pp = pkeep.data_ptr()
+            else:
+                pkeep = pos_np
+                pp = pos_np.ctypes.data
+        _check(lib.ptyc_add_positions(self._ctx, count, pp, ip, ik), self._ctx)
+        return self
+
+    # ----------------------------------------------------------------- sweep
+    def sweep(self, n_sweeps=1, order=None, batch_offsets=None, errors=False):
+        """Run sweeps; returns the running Fourier error per sweep when
+        ``errors`` (this synchronises), else None."""
+        lib = L.lib()
+        o, op = _i64(order)
+        b, bp = _i64(batch_offsets)
+        olen = 0 if o is None else len(o)
+        nb = 0 if b is None else len(b) - 1
+        err = np.zeros(n_sweeps, dtype=np.float64) if errors else None
+        ep = err.ctypes.data_as(C.POINTER(C.c_double)) if errors else None
+        _check(lib.ptyc_sweep(self._ctx, n_sweeps, op, olen, bp, nb, ep), self._ctx)
+        return err
+
+    def get_schedule(self):
+        """(order, batch_offsets) of the next default sweep."""
+        lib = L.lib()
+        nb = C.c_int64()
+        _check(lib.ptyc_get_schedule(self._ctx, None, None, C.byref(nb)), self._ctx)
+        n = self.num_positions
+        order = np.zeros(n, dtype=np.int64)
+        off = np.zeros(nb.value + 1, dtype=np.int64)
+        _check(lib.ptyc_get_schedule(self._ctx, order.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(nb)), self._ctx)
+        return order, off
+
+    # ---------------------------------------------------------------- state
+    def _get(self, fn, shape, device):
+        lib = L.lib()
+        if device:
+            out = torch.empty(shape, dtype=torch.complex64, device="cuda")
+            _check(fn(self._ctx, out.data_ptr(), L.PTYC_MEM_DEVICE), self._ctx)
+            return out
+        out = np.empty(shape, dtype=np.complex64)
+        _check(fn(self._ctx, out.ctypes.data, L.PTYC_MEM_HOST), self._ctx)
+        return out
+
+    def get_object(self, device=False):
+        return self._get(L.lib().ptyc_get_object, (self.h, self.w), device)
+
+    def get_probe(self, device=False):
+        return self._get(L.lib().ptyc_get_probe, (self.n, self.n), device)
+
+    def set_object(self, obj):
+        p, k, keep = _buffer(obj, np.complex64, torch.complex64 if torch is not None else None)
+        _check(L.lib().ptyc_set_object(self._ctx, p, k), self._ctx)
+
+    def set_probe(self, probe):
+        p, k, keep = _buffer(probe, np.complex64, torch.complex64 if torch is not None else None)
+        _check(L.lib().ptyc_set_probe(self._ctx, p, k), self._ctx)
+
+    @property
+    def num_positions(self) -> int:
+        return int(L.lib().ptyc_num_positions(self._ctx))
+
+    @property
+    def sweeps_done(self) -> int:
+        return int(L.lib().ptyc_sweep_count(self._ctx))
+
+    def synchronize(self):
+        _check(L.lib().ptyc_synchronize(self._ctx), self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            L.lib().ptyc_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- host helpers
+
+def colour(positions, n, max_batch=0):
+    """The library's greedy first-fit colouring (host only)."""
+    pos = np.ascontiguousarray(positions, dtype=np.int32)
+    out = np.zeros(len(pos), dtype=np.int32)
+    nc = C.c_int32()
+    _check(L.lib().ptyc_colour(len(pos), pos.ctypes.data, n, max_batch,
+                               out.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nc)))
+    return out, nc.value
+
+
+def check_batches(positions, n, order, batch_offsets) -> int:
+    """The library's host validator; returns the status code."""
+    pos = np.ascontiguousarray(positions, dtype=np.int32)
+    o, op = _i64(order)
+    b, bp = _i64(batch_offsets)
+    return int(L.lib().ptyc_check_batches(len(pos), pos.ctypes.data, n, op, len(o), bp, len(b) - 1))

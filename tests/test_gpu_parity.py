@@ -1,0 +1,289 @@
+"""GPU path against the FP64 oracle, through the C ABI (libptyc via the
+ctypes binding).  Every sweep is re-synced: the GPU starts from the oracle's
+state rounded to complex64, both run the same schedule, then object (over
+the loaded windows) and probe are compared in relative L2."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import sim
+from _parity import (RTOL, check_rows, engine_for, library_schedule, oracle_sweep, run_resynced,
+                     strict_schedule)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_10674_amd import _lib
+    _lib.lib()   # fails loudly if the HIP library is missing
+
+
+def _small(n, side, step, m, jitter=1, seed=5, photons=1e6, h=None, w=None):
+    pos = sim.raster_positions(side, step, n, m, jitter, seed)
+    return sim.make_workload(n, m, n * 0.3, 0.5 / (n * 0.3), pos, photons, seed, h=h, w=w)
+
+
+# ------------------------------------------------------------------ single update
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+def test_error_reduction_special_case(n):
+    """Constant complex probe, beta = 0: one update is the textbook
+    error-reduction projection, |F(c w')| = sqrt(I) with F(c w)'s phase;
+    and the GPU matches the oracle."""
+    rng = np.random.default_rng(n)
+    h, w = n + 3, n + 5
+    obj = (rng.standard_normal((h, w)) + 1j * rng.standard_normal((h, w))).astype(np.complex64)
+    c = np.complex64(0.7 * np.exp(0.3j))
+    probe = np.full((n, n), c, np.complex64)
+    inten = (rng.random((1, n, n)) * 50).astype(np.float32)
+    pos = np.array([[2, 4]], np.int32)
+    from paper_2308_10674_amd import Engine
+    eng = Engine(n, h, w, probe, obj, alpha=1.0, beta=0.0, mode="strict")
+    eng.add_positions(pos, inten)
+    eng.sweep(1, order=[0])
+    Og, Pg = eng.get_object(), eng.get_probe()
+    On, Pn, _, _ = oracle.sweep_strict(obj, probe, pos, inten, [0], 1.0, 0.0)
+    win = Og[2:2 + n, 4:4 + n].astype(np.complex128)
+    F = np.fft.fft2(c * win)
+    F0 = np.fft.fft2(c * obj[2:2 + n, 4:4 + n].astype(np.complex128))
+    assert oracle.rel_l2(np.abs(F), np.sqrt(inten[0].astype(np.float64))) < 1e-5
+    big = np.abs(F0) > 1e-3 * np.abs(F0).max()
+    assert np.max(np.abs(np.angle(F[big] / F0[big]))) < 1e-3
+    assert oracle.rel_l2(Og, On) < RTOL
+    np.testing.assert_array_equal(Pg, probe)                 # beta = 0
+    outside = np.ones((h, w), bool)
+    outside[2:2 + n, 4:4 + n] = False
+    np.testing.assert_array_equal(Og[outside], obj[outside])
+
+
+# ------------------------------------------------------------------ whole sweeps
+
+def test_config0_strict_resynced():
+    """32 px patterns, 10 x 10 raster, sequential ePIE, 10 sweeps."""
+    wl = sim.make_config(0)
+    eng = engine_for(wl)
+    rows, _ = run_resynced(eng, wl, 10, strict_schedule(wl), label="cfg0")
+    check_rows(rows)
+
+
+def test_config0_free_running_trajectory():
+    """Not re-synced: the FP32 trajectory stays close to the FP64 one
+    (reported; the bar is the running error, not the state)."""
+    wl = sim.make_config(0)
+    eng = engine_for(wl)
+    mask = oracle.union_mask(wl.positions, wl.n, wl.h, wl.w)
+    O, P = wl.object0, wl.probe0
+    for s in range(10):
+        order = sim.sweep_order(wl.seed, s, wl.count)
+        e = eng.sweep(1, order=order, errors=True)[0]
+        O, P, num, den = oracle.sweep_strict(O, P, wl.positions, wl.intensities, order)
+        ro = oracle.rel_l2(eng.get_object(), O, mask)
+        rp = oracle.rel_l2(eng.get_probe(), P)
+        print("free", s, ro, rp, e, num / den, flush=True)
+        assert abs(e - num / den) < 1e-3 * num / den
+    assert ro < 1e-3 and rp < 1e-3
+
+
+def test_coloured_128_resynced():
+    """128 px patterns on the 1024^2 object: first 600 raster positions,
+    the library's own colour batches, 3 sweeps."""
+    wl = sim.make_config(1, n_positions=600)
+    eng = engine_for(wl)
+    rows, _ = run_resynced(eng, wl, 3, library_schedule(eng), label="cfg1")
+    check_rows(rows)
+
+
+def test_coloured_256_resynced():
+    """256 px patterns on the 2048^2 object: every 30th position of the
+    20000-point Fermat spiral (spread over the whole object), 2 sweeps."""
+    c = sim.CONFIGS[2]
+    pos = sim.fermat_positions(20000, 6.0, 256, 2048)[::30]
+    wl = sim.make_workload(256, 2048, c["radius"], c["kappa"], pos, c["photons"], 1002, config=2)
+    eng = engine_for(wl)
+    order, off = eng.get_schedule()
+    assert np.diff(off).max() > 4
+    rows, _ = run_resynced(eng, wl, 2, library_schedule(eng), label="cfg2")
+    check_rows(rows)
+
+
+@pytest.mark.parametrize("n,mode", [(16, "strict"), (16, "coloured"), (64, "coloured"), (64, "strict")])
+def test_other_sizes(n, mode):
+    wl = _small(n, 8, n // 3, 4 * n)
+    eng = engine_for(wl, mode=mode)
+    sched = strict_schedule(wl) if mode == "strict" else library_schedule(eng)
+    check_rows(*run_resynced(eng, wl, 2, sched, label=f"n{n}{mode}"))
+
+
+def test_ragged_edges_and_nonsquare_object():
+    """Windows flush with the last row and column of a non-square object
+    whose width is not a multiple of anything convenient."""
+    n, h, w = 64, 300, 517
+    rng = np.random.default_rng(9)
+    pos = np.concatenate([rng.integers(0, [h - n + 1, w - n + 1], (30, 2)),
+                          [[h - n, w - n], [0, w - n], [h - n, 0], [0, 0]]]).astype(np.int32)
+    wl = sim.make_workload(n, None, 20.0, 0.025, pos, 1e6, 9, h=h, w=w)
+    eng = engine_for(wl)
+    check_rows(*run_resynced(eng, wl, 2, library_schedule(eng), label="ragged"))
+
+
+def test_live_growth_resynced():
+    """Live mode on the 128 px raster: reveal 200 positions, 2 sweeps, repeat."""
+    wl = sim.make_config(1, n_positions=600)
+    eng = engine_for(wl, count=0)
+    O, P = wl.object0, wl.probe0
+    for k in range(3):
+        cnt = 200 * (k + 1)
+        eng.add_positions(wl.positions[cnt - 200:cnt], wl.intensities[cnt - 200:cnt])
+        assert eng.num_positions == cnt
+        rows, (O, P) = run_resynced(eng, wl, 2, library_schedule(eng), count=cnt, start=(O, P),
+                                    label=f"live{cnt}")
+        check_rows(rows)
+
+
+def test_max_batch_cap_and_explicit_batches():
+    wl = sim.make_config(1, n_positions=300)
+    eng = engine_for(wl, max_batch=3)
+    order, off = eng.get_schedule()
+    assert np.diff(off).max() <= 3
+    check_rows(*run_resynced(eng, wl, 1, library_schedule(eng), label="cap3"))
+    # a hand-made schedule: a subset of positions in singleton and pair batches
+    sub = np.array([5, 200, 17, 250], np.int64)
+    assert not oracle.windows_overlap(wl.positions[5], wl.positions[200], wl.n)
+    check_rows(*run_resynced(eng, wl, 1, lambda s: (sub, np.array([0, 2, 3, 4])), label="explicit"))
+
+
+# ------------------------------------------------------------------ bit-level properties
+
+def test_default_schedule_matches_exported_and_is_deterministic():
+    wl = sim.make_config(1, n_positions=400)
+    a = engine_for(wl)
+    b = engine_for(wl)
+    order, off = a.get_schedule()
+    a.sweep(1)
+    b.sweep(1, order=order, batch_offsets=off)
+    np.testing.assert_array_equal(a.get_object(), b.get_object())
+    np.testing.assert_array_equal(a.get_probe(), b.get_probe())
+    # the next default schedule differs (fresh shuffle per sweep)
+    o2, f2 = a.get_schedule()
+    assert not np.array_equal(o2, order)
+    # replaying the same sweep from the same state gives the same bytes
+    a.set_object(wl.object0)
+    a.set_probe(wl.probe0)
+    a.sweep(1, order=order, batch_offsets=off)
+    np.testing.assert_array_equal(a.get_object(), b.get_object())
+    np.testing.assert_array_equal(a.get_probe(), b.get_probe())
+
+
+def test_growth_in_steps_equals_growth_at_once():
+    wl = sim.make_config(1, n_positions=500)
+    a = engine_for(wl, count=0)
+    for lo, hi in ((0, 120), (120, 121), (121, 500)):
+        a.add_positions(wl.positions[lo:hi], wl.intensities[lo:hi])
+    b = engine_for(wl)
+    oa, fa = a.get_schedule()
+    ob, fb = b.get_schedule()
+    np.testing.assert_array_equal(oa, ob)
+    np.testing.assert_array_equal(fa, fb)
+    a.sweep(2)
+    b.sweep(2)
+    np.testing.assert_array_equal(a.get_object(), b.get_object())
+    np.testing.assert_array_equal(a.get_probe(), b.get_probe())
+
+
+def test_restart_equals_uninterrupted():
+    """k sweeps, export, new context from the exported state, re-add the
+    data, m more sweeps == k+m sweeps (same explicit schedules)."""
+    wl = sim.make_config(1, n_positions=400)
+    ref = engine_for(wl)
+    scheds = []
+    for s in range(4):
+        scheds.append(ref.get_schedule())
+        ref.sweep(1)
+    a = engine_for(wl)
+    for o, f in scheds[:2]:
+        a.sweep(1, order=o, batch_offsets=f)
+    O, P = a.get_object(), a.get_probe()
+    a.close()
+    from paper_2308_10674_amd import Engine
+    b = Engine(wl.n, wl.h, wl.w, P, O, mode="coloured", seed=wl.seed)
+    b.add_positions(wl.positions, wl.intensities)
+    for o, f in scheds[2:]:
+        b.sweep(1, order=o, batch_offsets=f)
+    np.testing.assert_array_equal(b.get_object(), ref.get_object())
+    np.testing.assert_array_equal(b.get_probe(), ref.get_probe())
+
+
+def test_device_buffers_in_and_out():
+    import torch
+    wl = sim.make_config(0)
+    from paper_2308_10674_amd import Engine
+    dev = Engine(wl.n, wl.h, wl.w, torch.from_numpy(wl.probe0.astype(np.complex64)).cuda(),
+                 torch.from_numpy(wl.object0.astype(np.complex64)).cuda(), mode="strict", seed=wl.seed)
+    dev.add_positions(torch.from_numpy(wl.positions).cuda(), torch.from_numpy(wl.intensities).cuda())
+    host = engine_for(wl)
+    order = sim.sweep_order(wl.seed, 0, wl.count)
+    dev.sweep(1, order=order)
+    host.sweep(1, order=order)
+    Od = dev.get_object(device=True)
+    assert Od.is_cuda
+    np.testing.assert_array_equal(Od.cpu().numpy(), host.get_object())
+    np.testing.assert_array_equal(dev.get_probe(), host.get_probe())
+
+
+# ------------------------------------------------------------------ edge cases and errors
+
+def test_empty_and_noop_calls():
+    wl = sim.make_config(0)
+    eng = engine_for(wl, count=0)
+    err = eng.sweep(3, errors=True)
+    np.testing.assert_array_equal(err, 0.0)
+    np.testing.assert_array_equal(eng.get_object(), wl.object0.astype(np.complex64))
+    eng.add_positions(np.zeros((0, 2), np.int32), np.zeros((0, wl.n, wl.n), np.float32))
+    assert eng.num_positions == 0
+    eng.add_positions(wl.positions[:1], wl.intensities[:1])
+    eng.sweep(1, order=np.zeros(0, np.int64))
+    np.testing.assert_array_equal(eng.get_object(), wl.object0.astype(np.complex64))
+
+
+def test_error_paths():
+    from paper_2308_10674_amd import PtycError, _lib as L
+    wl = sim.make_config(1, n_positions=50)
+    eng = engine_for(wl, count=10)
+    bad = wl.positions[10:12].copy()
+    bad[1] = [wl.h - wl.n + 1, 0]
+    with pytest.raises(PtycError) as e:
+        eng.add_positions(bad, wl.intensities[10:12])
+    assert e.value.status == L.PTYC_ERR_BOUNDS
+    assert eng.num_positions == 10
+    inten = wl.intensities[10:12].copy()
+    inten[1, 3, 4] = -1.0
+    with pytest.raises(PtycError) as e:
+        eng.add_positions(wl.positions[10:12], inten)
+    assert e.value.status == L.PTYC_ERR_ARG
+    inten[1, 3, 4] = np.nan
+    with pytest.raises(PtycError):
+        eng.add_positions(wl.positions[10:12], inten)
+    assert eng.num_positions == 10
+    with pytest.raises(PtycError):   # overlapping windows in one batch
+        eng.sweep(1, order=[0, 1], batch_offsets=[0, 2])
+    with pytest.raises(PtycError):   # index not loaded
+        eng.sweep(1, order=[0, 10], batch_offsets=[0, 1, 2])
+    eng.sweep(1)                     # still healthy
+    assert eng.sweeps_done == 1
+
+
+def test_device_memory_cap_gives_oom(monkeypatch):
+    from paper_2308_10674_amd import Engine, PtycError, _lib as L
+    wl = sim.make_config(1, n_positions=50)
+    monkeypatch.setenv("PTYC_MAX_DEVICE_BYTES", str(10 << 20))
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0)      # 8 MiB object fits
+    with pytest.raises(PtycError) as e:
+        eng.add_positions(wl.positions, wl.intensities)         # the stack does not
+    assert e.value.status == L.PTYC_ERR_OOM
+    assert eng.num_positions == 0
