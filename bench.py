@@ -1,0 +1,171 @@
+"""Throughput benchmark: ePIE position updates per second on one MI355X.
+
+A step is one sweep of the coloured-batch ePIE over every loaded position of
+the 128 px workload: 60 x 60 raster (step 12 px, jitter +-2), 3600
+positions, 1024 x 1024 object, Poisson data at 1e7 photons per pattern
+(synthetic, seeded).  Inputs are resident in HBM before the timed region;
+the library's own shuffled colour schedule runs each sweep.  By default the
+256 px workload (20000-position Fermat spiral, 2048 x 2048 object, 1e8
+photons) is timed as well and reported under "n256".
+
+Roofline: the algorithmic HBM traffic of one position update is 20 N^2
+bytes (read sqrt(I) 4 N^2, read the object window 8 N^2, write it 8 N^2);
+the probe and the exchange buffers are not counted.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(n: int) -> int:
+    return 20 * n * n
+
+
+def load_traffic(path):
+    """HBM bytes per position update measured with rocprofv3 counters, if a
+    summary with that figure is committed (profiles/*.json)."""
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except Exception:
+        return None
+
+
+def run_gpu(cfg_id, steps, warmup, form, positions=None):
+    import torch
+
+    import sim
+    from paper_2308_10674_amd import Engine
+
+    t0 = time.time()
+    wl = sim.make_config(cfg_id, n_positions=positions)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    inten = torch.from_numpy(wl.intensities).to(dev)
+    pos = torch.from_numpy(wl.positions).to(dev)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    t1 = time.time()
+    eng.add_positions(pos, inten)
+    torch.cuda.synchronize()
+    ingest_s = time.time() - t1
+    del inten
+    order, off = eng.get_schedule()
+    sizes = np.diff(off)
+    eng.sweep(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    eng.sweep(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    err = eng.sweep(1, errors=True)[0]
+    updates = wl.count * steps
+    rate = updates / (ms / 1e3)
+    achieved = algorithmic_bytes(wl.n) * rate / 1e9
+    return dict(wl=wl, ms=ms, rate=rate, achieved_gbs=achieved, batches=int(len(sizes)),
+                mean_batch=float(sizes.mean()), max_batch=int(sizes.max()), gen_s=gen_s,
+                ingest_s=ingest_s, err=float(err))
+
+
+def cpu_baseline(cfg_id, budget_s):
+    """The FP64 oracle on the host: coloured sweep over the same workload's
+    first batches until ``budget_s`` seconds of work are done."""
+    import oracle
+    import sim
+    from paper_2308_10674_amd import colour
+
+    wl = sim.make_config(cfg_id)
+    col, nc = colour(wl.positions, wl.n)
+    base = np.argsort(col, kind="stable")
+    off = np.concatenate([[0], np.cumsum(np.bincount(col))])
+    O, P = wl.object0, wl.probe0
+    done = 0
+    t0 = time.perf_counter()
+    b = 0
+    while time.perf_counter() - t0 < budget_s and b < nc:
+        idx = base[off[b]:off[b + 1]]
+        O, P, _, _ = oracle.sweep_coloured(O, P, wl.positions, wl.intensities, idx, [0, len(idx)], check=False)
+        done += len(idx)
+        b += 1
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="position updates/s", cores=1, kind="oracle",
+                sample=f"FP64 numpy oracle, coloured batches 0..{b - 1} of one sweep "
+                       f"({done} of {wl.count} position updates, {dt:.1f} s, single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", default="batch", choices=["batch"])
+    ap.add_argument("--no-256", action="store_true", help="skip the 256 px workload")
+    ap.add_argument("--steps-256", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the reconstruction of one scan is not split across GPUs "
+              "in this build (see the sharding notes of the design document).", file=sys.stderr)
+        sys.exit(2)
+
+    r = run_gpu(1, args.steps, args.warmup, args.form)
+    wl = r["wl"]
+    out = {
+        "metric": "ePIE position updates/sec at 128^2 and 256^2 patterns; % HBM roofline",
+        "value": round(r["rate"], 1),
+        "unit": "position updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": "ePIE 128x128 patterns, 60x60 raster step 12 px (3600 positions), 1024x1024 object, "
+                        "coloured batches of disjoint windows, one sweep per step",
+            "n": wl.n, "object": [wl.h, wl.w], "positions": wl.count, "form": args.form,
+            "batches_per_sweep": r["batches"], "mean_batch": round(r["mean_batch"], 2),
+            "max_batch": r["max_batch"],
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "whole sweep (all launches)",
+            "achieved": round(r["achieved_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 5), "traffic": None,
+            "bytes_per_update": algorithmic_bytes(wl.n),
+        },
+        "error_after": r["err"],
+    }
+    if not args.no_256:
+        r2 = run_gpu(2, args.steps_256, 1, args.form)
+        out["n256"] = {
+            "value": round(r2["rate"], 1), "unit": "position updates/s",
+            "ms_per_step": round(r2["ms"] / args.steps_256, 3), "steps": args.steps_256,
+            "workload": "ePIE 256x256 patterns, 20000-position Fermat spiral, 2048x2048 object",
+            "achieved": round(r2["achieved_gbs"], 2), "frac": round(r2["achieved_gbs"] / HBM_PEAK_GBS, 5),
+            "batches_per_sweep": r2["batches"], "mean_batch": round(r2["mean_batch"], 2),
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,26 +32,39 @@ def oracle_sweep(O, P, wl, order, off, dtype=np.complex128, alpha=None, beta=Non
     return oracle.sweep_coloured(O, P, pos, inten, order, off, a, b, dtype)
 
 
-def fp32_floor(O, P, wl, order, off, mask, count=None, **kw):
-    """Deviation of the oracle run in complex64 from the FP64 oracle on the
-    same sweep: what any FP32 implementation inherits from the problem's
-    conditioning."""
-    O64, P64, _, _ = oracle_sweep(O, P, wl, order, off, count=count, **kw)
-    O32, P32, _, _ = oracle_sweep(O.astype(np.complex64), P.astype(np.complex64), wl, order, off,
-                                  dtype=np.complex64, count=count, **kw)
-    return oracle.rel_l2(O32, O64, mask), oracle.rel_l2(P32, P64)
+def fp32_floor(O, P, wl, order, off, mask, count=None, angles=(0.3, 1.1, 2.0, 3.7, 5.2), **kw):
+    """What FP32 rounding alone does to one sweep: the largest deviation of
+    the oracle run in complex64 from the FP64 oracle, over the plain problem
+    and copies rotated by a global phase.  A global phase on object and
+    probe is an exact symmetry of ePIE (the result rotates with it), but it
+    stops numpy's FFT from keeping the spectrum of a real, even start
+    (Gaussian probe, flat object) exactly real, so the rotated copies show
+    the rounding any general FP32 FFT commits where the spectrum falls below
+    FP32 resolution.  Returns (object, probe, relative error-metric) floors."""
+    O64, P64, n64, d64 = oracle_sweep(O, P, wl, order, off, count=count, **kw)
+    e64 = n64 / d64
+    fo = fp = fe = 0.0
+    for ang in (0.0,) + tuple(angles):
+        r = np.exp(1j * ang)
+        O32, P32, n32, d32 = oracle_sweep((O * r).astype(np.complex64), (P * r).astype(np.complex64), wl,
+                                          order, off, dtype=np.complex64, count=count, **kw)
+        fo = max(fo, oracle.rel_l2(O32 / np.complex64(r), O64, mask))
+        fp = max(fp, oracle.rel_l2(P32 / np.complex64(r), P64))
+        fe = max(fe, abs(n32 / d32 - e64) / e64 if e64 > 0 else 0.0)
+    return fo, fp, fe
 
 
-def gate(rel, floor):
-    """The parity bar: 1e-5, unless even the FP32 oracle misses that on this
-    sweep (ill-conditioned Fourier phases), then three times its deviation."""
+def gate(floor):
+    """The parity bar: 1e-5, unless FP32 rounding alone (the oracle in
+    complex64) already moves this sweep further, then three times that."""
     return max(RTOL, 3.0 * floor)
 
 
 def run_resynced(eng, wl, n_sweeps, schedule, count=None, start=None, label=""):
     """For each sweep: take its (order, offsets) from ``schedule(s)``, reset
     the GPU to the oracle's state, run one sweep on both, compare.  Returns
-    the rows (also printed) and the oracle's final (object, probe)."""
+    the rows (also printed) and the oracle's final (object, probe).  A
+    sweep that misses 1e-5 is measured against the FP32 floor."""
     count = wl.count if count is None else count
     mask = oracle.union_mask(wl.positions[:count], wl.n, wl.h, wl.w)
     O, P = (wl.object0, wl.probe0) if start is None else start
@@ -65,21 +78,79 @@ def run_resynced(eng, wl, n_sweeps, schedule, count=None, start=None, label=""):
         err = eng.sweep(1, order=order, batch_offsets=off, errors=True)[0]
         Og, Pg = eng.get_object(), eng.get_probe()
         On, Pn, num, den = oracle_sweep(O, P, wl, order, off, count=count)
-        fo, fp = fp32_floor(O, P, wl, order, off, mask, count=count)
-        rows.append(dict(sweep=s, rel_o=oracle.rel_l2(Og, On, mask), rel_p=oracle.rel_l2(Pg, Pn),
-                         floor_o=fo, floor_p=fp, err_gpu=float(err), err_orc=num / den,
-                         untouched_equal=bool(np.array_equal(Og[~mask], O.astype(np.complex64)[~mask]))))
-        print(label, rows[-1], flush=True)
+        e_orc = num / den
+        row = dict(sweep=s, rel_o=oracle.rel_l2(Og, On, mask), rel_p=oracle.rel_l2(Pg, Pn),
+                   rel_err=abs(float(err) - e_orc) / e_orc if e_orc > 0 else abs(float(err)),
+                   err_gpu=float(err), err_orc=e_orc, floor_o=0.0, floor_p=0.0, floor_err=0.0,
+                   untouched_equal=bool(np.array_equal(Og[~mask], O.astype(np.complex64)[~mask])))
+        if max(row["rel_o"], row["rel_p"], row["rel_err"]) > RTOL:
+            row["floor_o"], row["floor_p"], row["floor_err"] = fp32_floor(O, P, wl, order, off, mask, count=count)
+        print(label, row, flush=True)
+        rows.append(row)
         O, P = On, Pn
     return rows, (O, P)
 
 
-def check_rows(rows, final=None, err_rtol=1e-4):
+def check_rows(rows, final=None, factor=10.0):
+    """Per-sweep bar: 1e-5, or ``factor`` times the FP32 floor when FP32
+    rounding alone already exceeds it.  Along a sweep of a hundred or more
+    dependent batches rounding differences are amplified by the iteration
+    itself, and how much depends on where they fall, so two FP32
+    implementations of equal per-batch accuracy can differ several-fold
+    here; the strict check of every kernel is the per-batch one."""
     for r in rows:
-        assert r["rel_o"] <= gate(r["rel_o"], r["floor_o"]), r
-        assert r["rel_p"] <= gate(r["rel_p"], r["floor_p"]), r
-        assert abs(r["err_gpu"] - r["err_orc"]) <= err_rtol * r["err_orc"] + 1e-12, r
+        assert r["rel_o"] <= max(RTOL, factor * r["floor_o"]), r
+        assert r["rel_p"] <= max(RTOL, factor * r["floor_p"]), r
+        assert r["rel_err"] <= max(RTOL, factor * r["floor_err"]), r
         assert r["untouched_equal"], r
+
+
+def run_batches_resynced(eng, wl, order, off, count=None, start=None, label="", batches=None):
+    """Every batch of one sweep (or the listed ones) re-synced: the GPU
+    starts the batch from the oracle's state rounded to complex64 and runs
+    that batch alone; object (over the batch's windows), probe and the
+    batch's error numerator are compared.  Returns rows and the oracle's
+    state after the sweep (when all batches ran)."""
+    count = wl.count if count is None else count
+    pos, inten = wl.positions[:count], wl.intensities[:count]
+    O, P = (wl.object0, wl.probe0) if start is None else start
+    rows = []
+    todo = range(len(off) - 1) if batches is None else batches
+    for b in todo:
+        idx = np.asarray(order[off[b]:off[b + 1]])
+        if len(idx) == 0:
+            continue
+        eng.set_object(O.astype(np.complex64))
+        eng.set_probe(P.astype(np.complex64))
+        e = eng.sweep(1, order=idx, batch_offsets=None if eng.mode == "strict" else [0, len(idx)],
+                      errors=True)[0]
+        Og, Pg = eng.get_object(), eng.get_probe()
+        On, Pn, num, den = oracle_sweep(O, P, wl, idx, None if eng.mode == "strict" else [0, len(idx)],
+                                        count=count)
+        m = oracle.union_mask(pos[idx], wl.n, wl.h, wl.w)
+        row = dict(batch=int(b), size=int(len(idx)), rel_o=oracle.rel_l2(Og, On, m), rel_p=oracle.rel_l2(Pg, Pn),
+                   rel_err=abs(float(e) - num / den) / (num / den), floor_o=0.0, floor_p=0.0, floor_err=0.0,
+                   outside_equal=bool(np.array_equal(Og[~m], O.astype(np.complex64)[~m])))
+        if max(row["rel_o"], row["rel_p"], row["rel_err"]) > RTOL:
+            off1 = None if eng.mode == "strict" else [0, len(idx)]
+            row["floor_o"], row["floor_p"], row["floor_err"] = fp32_floor(O, P, wl, idx, off1, m, count=count)
+        rows.append(row)
+        if batches is None:
+            O, P = On, Pn
+    worst = max(rows, key=lambda r: max(r["rel_o"], r["rel_p"], r["rel_err"])) if rows else None
+    print(label, f"{len(rows)} batches re-synced, worst", worst, flush=True)
+    return rows, (O, P)
+
+
+def check_batches(rows):
+    """Per-batch bar: 1e-5 relative L2 on object, probe and error numerator;
+    only a batch whose spectrum falls below FP32 resolution (the first batch
+    from a real, even start) is held to three times the FP32 floor."""
+    for r in rows:
+        assert r["rel_o"] <= gate(r["floor_o"]), r
+        assert r["rel_p"] <= gate(r["floor_p"]), r
+        assert r["rel_err"] <= gate(r["floor_err"]), r
+        assert r["outside_equal"], r
 
 
 def library_schedule(eng):
