@@ -55,7 +55,7 @@ def run_gpu(cfg_id, steps, warmup, form, positions=None):
     dev = torch.device("cuda:0")
     inten = torch.from_numpy(wl.intensities).to(dev)
     pos = torch.from_numpy(wl.positions).to(dev)
-    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed, form=form)
     t1 = time.time()
     eng.add_positions(pos, inten)
     torch.cuda.synchronize()
@@ -112,12 +112,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="batch", choices=["batch"])
+    ap.add_argument("--form", default="batch", choices=["batch", "persistent"],
+                    help="batch: three launches per batch; persistent: one cooperative kernel per sweep")
     ap.add_argument("--no-256", action="store_true", help="skip the 256 px workload")
     ap.add_argument("--steps-256", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device copy kernel (x -> -x), three times, to scale "
+                         "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "neg copy", "bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the reconstruction of one scan is not split across GPUs "
               "in this build (see the sharding notes of the design document).", file=sys.stderr)
@@ -146,7 +159,8 @@ def main():
             "max_batch": r["max_batch"],
         },
         "roofline": {
-            "bound": "hbm", "kernel": "whole sweep (all launches)",
+            "bound": "hbm",
+            "kernel": "k_sweep<128> (one launch per sweep)" if args.form == "persistent" else "all launches of a sweep",
             "achieved": round(r["achieved_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 5), "traffic": None,
             "bytes_per_update": algorithmic_bytes(wl.n),

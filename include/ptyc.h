@@ -148,6 +148,19 @@ int ptyc_get_probe(ptyc_ctx* ctx, void* out, int mem_kind);
 int ptyc_set_object(ptyc_ctx* ctx, const void* in, int mem_kind);
 int ptyc_set_probe(ptyc_ctx* ctx, const void* in, int mem_kind);
 
+/* Launch form of a sweep: PTYC_FORM_BATCH (the default) launches three
+ * kernels per batch; PTYC_FORM_PERSISTENT runs each sweep as one cooperative
+ * kernel whose stages are separated by grid-wide barriers.  Both produce the
+ * same bytes.  PTYC_FORM_DEFAULT selects PTYC_FORM_BATCH.  Errors:
+ * PTYC_ERR_ARG for an unknown form or a persistent grid the device cannot
+ * hold. */
+#define PTYC_FORM_DEFAULT 0
+#define PTYC_FORM_BATCH 1
+#define PTYC_FORM_PERSISTENT 2
+int ptyc_set_form(ptyc_ctx* ctx, int form);
+/* The current launch form (-1 for a NULL context). */
+int ptyc_get_form(const ptyc_ctx* ctx);
+
 /* Number of loaded positions (-1 for a NULL context). */
 int64_t ptyc_num_positions(const ptyc_ctx* ctx);
 /* Number of completed sweeps (drives the default shuffle). */

@@ -17,6 +17,9 @@ PTYC_MEM_HOST = 0
 PTYC_MEM_DEVICE = 1
 PTYC_MODE_STRICT = 0
 PTYC_MODE_COLOURED = 1
+PTYC_FORM_DEFAULT = 0
+PTYC_FORM_BATCH = 1
+PTYC_FORM_PERSISTENT = 2
 PTYC_I_IS_SQRT = 1
 PTYC_I_CENTERED = 2
 
@@ -49,6 +52,8 @@ SIGNATURES = {
     "ptyc_get_probe": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_set_object": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_set_probe": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_set_form": (C.c_int, [_P, C.c_int]),
+    "ptyc_get_form": (C.c_int, [_P]),
     "ptyc_num_positions": (C.c_int64, [_P]),
     "ptyc_sweep_count": (C.c_int64, [_P]),
     "ptyc_synchronize": (C.c_int, [_P]),

@@ -32,7 +32,9 @@ struct ptyc_ctx {
     int device = 0;
     bool poisoned = false;
     std::string err;
-    Shape shape{};
+    int form = kFormBatch;          // launch form of a sweep
+    int capacity = 0;               // co-resident workgroups of the persistent kernel
+    Shape sb{}, sp{};               // work split of the per-batch and persistent forms
 
     // device state
     DevBuf obj, probe, tw;
@@ -42,15 +44,17 @@ struct ptyc_ctx {
     int64_t slots = 0;
     DevBuf pmax_part;
     DevBuf order;                    // int64 [order_cap]
+    DevBuf offs;                     // int64 batch offsets of the persistent form
     DevBuf err_part, err_dev;
     DevBuf bad;                      // int flag for ingest validation
+    DevBuf sync;                     // [0] barrier counter, [1] barrier fault flag
     DevBuf staging;                  // host intensities staged on the device
 
     // host state
     std::vector<int32_t> h_pos;      // 2 per position
     Colouring* colouring = nullptr;
     int64_t sweeps_done = 0;
-    int64_t* pinned_order = nullptr; // pinned upload buffer
+    int64_t* pinned_order = nullptr; // pinned upload buffer (orders, then offsets)
     size_t pinned_bytes = 0;
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
@@ -167,6 +171,11 @@ void default_schedule(const ptyc_ctx* c, int64_t sweep, std::vector<int64_t>& or
     }
 }
 
+const Shape& shape_of(const ptyc_ctx* c) { return c->form == kFormPersistent ? c->sp : c->sb; }
+int max_row_blocks(const ptyc_ctx* c) { return std::max(c->sb.row_blocks, c->sp.row_blocks); }
+int max_col_blocks(const ptyc_ctx* c) { return std::max(c->sb.col_blocks, c->sp.col_blocks); }
+int max_probe_blocks(const ptyc_ctx* c) { return std::max(c->sb.probe_blocks, c->sp.probe_blocks); }
+
 BatchArgs base_args(ptyc_ctx* c) {
     BatchArgs a{};
     a.obj = (cf*)c->obj.p;
@@ -181,7 +190,8 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.dprobe = (cf*)c->dprobe.p;
     a.winmax = (float*)c->winmax.p;
     a.pmax_part = (float*)c->pmax_part.p;
-    a.npmax = c->shape.probe_blocks;
+    a.npmax = shape_of(c).probe_blocks;
+    a.row_blocks = shape_of(c).row_blocks;
     a.err_part = (double*)c->err_part.p;
     a.alpha = c->cfg.alpha;
     a.beta = c->cfg.beta;
@@ -197,7 +207,20 @@ int copy_square_in(ptyc_ctx* c, DevBuf& dst, const void* src, size_t bytes, int 
 int refresh_probe_max(ptyc_ctx* c) {
     BatchArgs a = base_args(c);
     a.bsize = 0;
-    HIPCHK(c, launch_probe_reduce(c->cfg.n, a, c->stream));
+    HIPCHK(c, launch_probe_reduce(c->cfg.n, a, c->form, c->stream));
+    return PTYC_OK;
+}
+
+// after a synchronisation: did a persistent sweep give up on a barrier?
+int check_fault(ptyc_ctx* c) {
+    if (!c->sync.p) return PTYC_OK;
+    unsigned v[2] = {0, 0};
+    HIPCHK(c, hipMemcpy(v, c->sync.p, sizeof(v), hipMemcpyDeviceToHost));
+    if (v[1]) {
+        c->poisoned = true;
+        c->err = "persistent sweep kernel: a grid barrier wait exceeded its bound (results invalid)";
+        return PTYC_ERR_HIP;
+    }
     return PTYC_OK;
 }
 
@@ -230,7 +253,8 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     ptyc_ctx* c = new ptyc_ctx();
     c->cfg = *cfg;
     c->stream = (hipStream_t)hip_stream;
-    c->shape = shape_for(cfg->n);
+    c->sb = shape_for(cfg->n, kFormBatch);
+    c->sp = shape_for(cfg->n, kFormPersistent);
     c->dev_limit = env_limit();
     c->colouring = new Colouring(cfg->n, max_batch_of(c));
     (void)hipGetDevice(&c->device);
@@ -246,8 +270,14 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     if ((rc = ensure(c, c->obj, obj_bytes)) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->probe, pr_bytes)) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->tw, n * sizeof(cf))) != PTYC_OK) return bail(rc);
-    if ((rc = ensure(c, c->pmax_part, c->shape.probe_blocks * sizeof(float))) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->pmax_part, max_probe_blocks(c) * sizeof(float))) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->bad, sizeof(int))) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->sync, 2 * sizeof(unsigned))) != PTYC_OK) return bail(rc);
+    if ((e = hipMemsetAsync(c->sync.p, 0, 2 * sizeof(unsigned), c->stream)) != hipSuccess) {
+        hip_fail(c, e, "hipMemsetAsync(sync)");
+        return bail(PTYC_ERR_HIP);
+    }
+    c->capacity = persistent_capacity(n);
     // twiddles exp(-2 pi i m / n) in double precision, rounded once to float
     std::vector<cf> tw((size_t)n);
     for (int m = 0; m < n; ++m) {
@@ -270,8 +300,8 @@ void ptyc_destroy(ptyc_ctx* c) {
     if (!c) return;
     if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
-                      &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->err_part,
-                      &c->err_dev, &c->bad, &c->staging};
+                      &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
+                      &c->err_dev, &c->bad, &c->sync, &c->staging};
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -289,8 +319,21 @@ int ptyc_synchronize(ptyc_ctx* c) {
     int rc = usable(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PTYC_OK;
+    return check_fault(c);
 }
+
+int ptyc_set_form(ptyc_ctx* c, int form) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (form == 0) form = kFormBatch;
+    if (form != kFormBatch && form != kFormPersistent) return fail(c, PTYC_ERR_ARG, "unknown launch form");
+    if (form == kFormPersistent && c->capacity <= 0)
+        return fail(c, PTYC_ERR_ARG, "the persistent form cannot be launched on this device");
+    c->form = form;
+    return refresh_probe_max(c);
+}
+
+int ptyc_get_form(const ptyc_ctx* c) { return c ? c->form : -1; }
 
 int ptyc_add_positions(ptyc_ctx* c, int64_t count, const int32_t* pos_yx, const float* inten,
                        int mem_kind) {
@@ -416,6 +459,9 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
         }
     }
     const int64_t olen = (int64_t)orders[0].size();
+    const int64_t nb = (int64_t)offs[0].size() - 1;
+    for (int s = 1; s < n_sweeps; ++s)
+        if ((int64_t)offs[(size_t)s].size() - 1 != nb) return fail(c, PTYC_ERR_ARG, "internal: batch count varies");
     int64_t max_b = 1;
     for (int s = 0; s < n_sweeps; ++s)
         for (size_t b = 0; b + 1 < offs[(size_t)s].size(); ++b)
@@ -426,31 +472,37 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
     if (max_b > c->slots) {
         if ((rc = ensure(c, c->scratch, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
         if ((rc = ensure(c, c->dprobe, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
-        if ((rc = ensure(c, c->winmax, (size_t)max_b * c->shape.row_blocks * sizeof(float))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->winmax, (size_t)max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
         c->slots = max_b;
     }
     const size_t obytes = (size_t)n_sweeps * olen * sizeof(int64_t);
+    const size_t fbytes = (size_t)n_sweeps * (nb + 1) * sizeof(int64_t);
     if (c->upload_pending) {
         HIPCHK(c, hipEventSynchronize(c->upload_done));
         c->upload_pending = false;
     }
     if ((rc = ensure(c, c->order, obytes)) != PTYC_OK) return rc;
-    if ((rc = ensure(c, c->err_part, (size_t)olen * c->shape.col_blocks * sizeof(double))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->offs, fbytes)) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_part, (size_t)olen * max_col_blocks(c) * sizeof(double))) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->err_dev, (size_t)n_sweeps * sizeof(double))) != PTYC_OK) return rc;
-    if (c->pinned_bytes < obytes) {
+    if (c->pinned_bytes < obytes + fbytes) {
         if (c->pinned_order) (void)hipHostFree(c->pinned_order);
         c->pinned_order = nullptr;
         c->pinned_bytes = 0;
-        hipError_t e = hipHostMalloc((void**)&c->pinned_order, obytes, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void**)&c->pinned_order, obytes + fbytes, hipHostMallocDefault);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(c, PTYC_ERR_OOM, "pinned host allocation failed");
         }
-        c->pinned_bytes = obytes;
+        c->pinned_bytes = obytes + fbytes;
     }
-    for (int s = 0; s < n_sweeps; ++s)
+    int64_t* pin_off = c->pinned_order + (size_t)n_sweeps * olen;
+    for (int s = 0; s < n_sweeps; ++s) {
         std::memcpy(c->pinned_order + (size_t)s * olen, orders[(size_t)s].data(), (size_t)olen * sizeof(int64_t));
+        std::memcpy(pin_off + (size_t)s * (nb + 1), offs[(size_t)s].data(), (size_t)(nb + 1) * sizeof(int64_t));
+    }
     HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, obytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->offs.p, pin_off, fbytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
     c->upload_pending = true;
 
@@ -458,15 +510,25 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
     for (int s = 0; s < n_sweeps; ++s) {
         BatchArgs a = base_args(c);
         a.order = (const int64_t*)c->order.p + (size_t)s * olen;
-        const auto& f = offs[(size_t)s];
-        for (size_t b = 0; b + 1 < f.size(); ++b) {
-            a.off = f[b];
-            a.bsize = (int)(f[b + 1] - f[b]);
-            if (a.bsize == 0) continue;
-            HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
+        if (c->form == kFormPersistent) {
+            SweepCtl ctl{};
+            ctl.offs = (const int64_t*)c->offs.p + (size_t)s * (nb + 1);
+            ctl.nb = (int)nb;
+            ctl.bar = (unsigned*)c->sync.p;
+            ctl.fault = (int*)((unsigned*)c->sync.p + 1);
+            ctl.nblocks = (unsigned)c->capacity;
+            HIPCHK(c, launch_sweep(c->cfg.n, a, ctl, (int)max_b, c->stream));
+        } else {
+            const auto& f = offs[(size_t)s];
+            for (size_t b = 0; b + 1 < f.size(); ++b) {
+                a.off = f[b];
+                a.bsize = (int)(f[b + 1] - f[b]);
+                if (a.bsize == 0) continue;
+                HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
+            }
         }
         if (err_out)
-            HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, olen * c->shape.col_blocks, a.order, olen,
+            HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, olen * shape_of(c).col_blocks, a.order, olen,
                                         (const double*)c->sum_i.p, (double*)c->err_dev.p + s, c->stream));
     }
     c->sweeps_done += n_sweeps;
@@ -474,6 +536,7 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
         HIPCHK(c, hipMemcpyAsync(err_out, c->err_dev.p, (size_t)n_sweeps * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        return check_fault(c);
     }
     return PTYC_OK;
 }
@@ -484,7 +547,7 @@ int ptyc_get_object(ptyc_ctx* c, void* out, int kind) {
     if (!out || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad output buffer or mem_kind");
     HIPCHK(c, hipMemcpyAsync(out, c->obj.p, (size_t)c->cfg.h * c->cfg.w * sizeof(cf), from_dev(kind), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PTYC_OK;
+    return check_fault(c);
 }
 
 int ptyc_get_probe(ptyc_ctx* c, void* out, int kind) {
@@ -493,7 +556,7 @@ int ptyc_get_probe(ptyc_ctx* c, void* out, int kind) {
     if (!out || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad output buffer or mem_kind");
     HIPCHK(c, hipMemcpyAsync(out, c->probe.p, (size_t)c->cfg.n * c->cfg.n * sizeof(cf), from_dev(kind), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PTYC_OK;
+    return check_fault(c);
 }
 
 int ptyc_set_object(ptyc_ctx* c, const void* in, int kind) {

@@ -21,26 +21,41 @@ struct BatchArgs {
     int bsize;                // positions in this batch
     cf* scratch;              // [slots][n][n] spectrum exchange between stages
     cf* dprobe;               // [slots][n][n] per-position probe increments
-    float* winmax;            // [slots][row blocks] partial max |S_j O|^2
-    float* pmax_part;         // [probe blocks] partial max |P|^2 of the current probe
-    int npmax;                // number of probe blocks
+    float* winmax;            // [slots][row_blocks] partial max |S_j O|^2
+    int row_blocks;           // forward row items per position (winmax stride)
+    float* pmax_part;         // [npmax] partial max |P|^2 of the current probe
+    int npmax;                // number of probe row blocks
     double* err_part;         // [order_len][column blocks] error partial sums
     float alpha, beta;
 };
 
-// Tile shapes per pattern size: rows per row-stage workgroup, columns per
-// column-stage workgroup (each workgroup has rows*N2 or cols*N2 threads).
+// Launch forms of a sweep.
+enum : int { kFormBatch = 1, kFormPersistent = 2 };
+
+// Work split per pattern size and launch form.
 struct Shape {
-    int row_blocks;   // workgroups per position in the row stages
-    int col_blocks;   // workgroups per position in the column stage
-    int probe_blocks; // workgroups of the probe reduction
+    int row_blocks;   // row items per position (winmax entries per slot)
+    int col_blocks;   // column items per position (error partials per position)
+    int probe_blocks; // probe items (pmax_part entries)
+};
+
+// Controls of the persistent sweep kernel.
+struct SweepCtl {
+    const int64_t* offs;  // [nb + 1] batch offsets into the order (device)
+    int nb;
+    unsigned* bar;        // arrival counter, zeroed by the launch
+    int* fault;           // raised when a barrier wait exceeds its bound
+    unsigned nblocks;     // in: co-resident capacity; the launch uses min(need, capacity)
 };
 
 bool supported_n(int n);
-Shape shape_for(int n);
+Shape shape_for(int n, int form);
 
 hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s);
-hipError_t launch_probe_reduce(int n, const BatchArgs& a, hipStream_t s);  // bsize 0: max only
+// the partial maxima of |P|^2 of the current probe (no update)
+hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s);
+int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel
+hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s);
 hipError_t launch_ingest(int n, const float* src, float* sqrt_i_dst, double* sum_i_dst,
                          int64_t count, bool is_sqrt, bool centred, int* bad_flag,
                          hipStream_t s);

@@ -1,18 +1,27 @@
 // HIP kernels of the ePIE position update for gfx950.
 //
-// One batch of positions with pairwise disjoint windows runs in four
-// launches (the stage split lets an N x N spectrum span several workgroups):
-//   rows_fwd   psi = P * S_j O, 1D FFT of every row           -> scratch
-//   cols       1D FFT of every column, modulus replacement with sqrt(I_j)
+// One batch of positions with pairwise disjoint windows is updated in three
+// stages (an N x N spectrum spans several workgroups, so the 2D transform is
+// split into a row pass and a column pass with an exchange buffer between):
+//   rows_fwd   psi = P * S_j O and the 1D FFT of each row       -> scratch
+//   cols       1D FFT of each column, modulus replacement with sqrt(I_j)
 //              and the error partial, inverse 1D FFT of the column -> scratch
-//   rows_inv   inverse 1D FFT of every row, scale 1/N^2, Delta = psi' - psi,
-//              object step into O and probe increment into dprobe
-//   probe      P += beta/|B| * sum of the batch's increments (slot order),
-//              and the partial maxima of |P|^2 for the next batch
-// The method is the ePIE update of Maiden & Rodenburg 2009 as used in the
-// paper's "ePIE Implementation" section; the batch semantics (shared probe
-// inside a batch, batch-mean probe step) make batch members commute.
+//   rows_inv   inverse 1D FFT of each row, psi' = ... / N^2, Delta = psi' - psi,
+//              object step into O; one workgroup owns a block of probe rows
+//              for every position of the batch and sums their increments
+//              conj(S_j O) Delta / max|S_j O|^2 in slot order, then writes
+//              P_{b+1} = P_b + beta/|B| * sum and the block's max |P_{b+1}|^2
+// The method is the ePIE update (Maiden & Rodenburg 2009) that the paper's
+// "ePIE Implementation" section uses; inside a batch every position sees the
+// same probe and the probe moves by the batch mean of the increments, so the
+// members of a batch commute.
+//
+// Launch forms: per batch, three kernel launches (k_rows_fwd, k_cols,
+// k_rows_inv); or one cooperative kernel per sweep (k_sweep) that runs the
+// same stage functions separated by grid-wide barriers.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernels.h"
 
@@ -60,39 +69,97 @@ __device__ inline double block_sum(double v, double* sh) {
 #pragma unroll
         for (int i = 0; i < NT / kWave; ++i) s += sh[i];
     }
+    __syncthreads();
     return s;
 }
 
-// rows per row-stage workgroup / columns per column-stage workgroup
+// ---------------------------------------------------------------- tiles
+// Forward row stage: RB rows of one position per workgroup; column stage: CB
+// columns.  Small tiles spread a position over many compute units (a batch
+// holds only a few dozen positions, so the stages are latency-bound).
+#ifndef PTYC_RB64
+#define PTYC_RB64 16
+#endif
+#ifndef PTYC_CB64
+#define PTYC_CB64 16
+#endif
+#ifndef PTYC_RB128
+#define PTYC_RB128 16
+#endif
+#ifndef PTYC_CB128
+#define PTYC_CB128 16
+#endif
+#ifndef PTYC_RB256
+#define PTYC_RB256 16
+#endif
+#ifndef PTYC_CB256
+#define PTYC_CB256 16
+#endif
 template <int N> struct Tile;
 template <> struct Tile<16>  { static constexpr int RB = 16, CB = 16; };
 template <> struct Tile<32>  { static constexpr int RB = 32, CB = 32; };
-template <> struct Tile<64>  { static constexpr int RB = 32, CB = 32; };
-template <> struct Tile<128> { static constexpr int RB = 32, CB = 32; };
-template <> struct Tile<256> { static constexpr int RB = 16, CB = 16; };
+template <> struct Tile<64>  { static constexpr int RB = PTYC_RB64, CB = PTYC_CB64; };
+template <> struct Tile<128> { static constexpr int RB = PTYC_RB128, CB = PTYC_CB128; };
+template <> struct Tile<256> { static constexpr int RB = PTYC_RB256, CB = PTYC_CB256; };
 
-template <int N> struct Geo {
+// Inverse row stage: R rows for S slots at a time (S*R*N2 threads); for the
+// probe step thread i < R*N owns element i of the block's R rows.
+#ifndef PTYC_IR128
+#define PTYC_IR128 1
+#endif
+#ifndef PTYC_IS128
+#define PTYC_IS128 32
+#endif
+#ifndef PTYC_IR256
+#define PTYC_IR256 1
+#endif
+#ifndef PTYC_IS256
+#define PTYC_IS256 32
+#endif
+template <int N> struct ITile;
+template <> struct ITile<16>  { static constexpr int R = 4, S = 4; };
+template <> struct ITile<32>  { static constexpr int R = 4, S = 8; };
+template <> struct ITile<64>  { static constexpr int R = 4, S = 8; };
+template <> struct ITile<128> { static constexpr int R = PTYC_IR128, S = PTYC_IS128; };
+template <> struct ITile<256> { static constexpr int R = PTYC_IR256, S = PTYC_IS256; };
+
+// Tiles of the persistent form: one workgroup size for all stages (B rows
+// or columns in the forward stages; R rows for S slots in the inverse stage).
+template <int N> struct PTile;
+template <> struct PTile<16>  { static constexpr int B = 16, R = 4, S = 4; };
+template <> struct PTile<32>  { static constexpr int B = 32, R = 4, S = 8; };
+template <> struct PTile<64>  { static constexpr int B = 32, R = 4, S = 8; };
+template <> struct PTile<128> { static constexpr int B = 32, R = 2, S = 16; };
+template <> struct PTile<256> { static constexpr int B = 16, R = 1, S = 16; };
+
+template <int N, int RB> struct RowG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
-    static constexpr int RB = Tile<N>::RB, CB = Tile<N>::CB;
-    static constexpr int G = N / RB;          // row blocks per position
-    static constexpr int GC = N / CB;         // column blocks per position
-    static constexpr int NT_ROW = RB * T;     // threads per row-stage workgroup
-    static constexpr int NT_COL = CB * T;     // threads per column-stage workgroup
-    static constexpr int NT_PROBE = 256;
-    static constexpr int PB = (N * N + NT_PROBE - 1) / NT_PROBE;  // probe blocks
+    static constexpr int G = N / RB, NT = RB * T;
+    static_assert(N % RB == 0 && NT % kWave == 0, "row tile");
+};
+template <int N, int CB> struct ColG {
+    static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
+    static constexpr int GC = N / CB, NT = CB * T;
+    static_assert(N % CB == 0 && NT % kWave == 0, "column tile");
+};
+template <int N, int R_ = ITile<N>::R, int S_ = ITile<N>::S> struct InvG {
+    static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
+    static constexpr int R = R_, S = S_;
+    static constexpr int NT = S * R * T, GI = N / R;
+    static_assert(R * N <= NT && NT % kWave == 0 && N % R == 0, "inverse tile");
 };
 
 // ---------------------------------------------------------------- stage 1
-template <int N>
-__global__ __launch_bounds__(Geo<N>::NT_ROW) void k_rows_fwd(BatchArgs a) {
-    using g = Geo<N>;
-    __shared__ cf lds[g::RB * Lds<N>::LINE];
-    __shared__ float red[g::NT_ROW / kWave];
-    const int slot = blockIdx.x / g::G, rb = blockIdx.x % g::G;
+// psi = P * S_j O for rows rb*RB .. rb*RB+RB-1 of slot `slot`, 1D FFT of
+// each row, spectrum rows to scratch; partial max |S_j O|^2 to winmax.
+template <int N, int RB>
+__device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds,
+                                               float* red) {
+    using g = RowG<N, RB>;
     const int64_t j = a.order[a.off + slot];
     const int2 p0 = a.pos[j];
     const int t = threadIdx.x % g::T, rl = threadIdx.x / g::T;
-    const int r = rb * g::RB + rl;
+    const int r = rb * RB + rl;
     const cf* orow = a.obj + (size_t)(p0.x + r) * a.w + p0.y;
     const cf* prow = a.probe + (size_t)r * N;
     cf v[g::N1];
@@ -113,120 +180,243 @@ __global__ __launch_bounds__(Geo<N>::NT_ROW) void k_rows_fwd(BatchArgs a) {
     for (int mm = 0; mm < g::N1 / g::N2; ++mm)
 #pragma unroll
         for (int k2 = 0; k2 < g::N2; ++k2) srow[(t + g::N2 * mm) + g::N1 * k2] = v[mm * g::N2 + k2];
-    m = block_max<g::NT_ROW>(m, red);
-    if (threadIdx.x == 0) a.winmax[slot * g::G + rb] = m;
+    m = block_max<g::NT>(m, red);
+    if (threadIdx.x == 0) a.winmax[slot * a.row_blocks + rb] = m;
 }
 
 // ---------------------------------------------------------------- stage 2
-template <int N>
-__global__ __launch_bounds__(Geo<N>::NT_COL) void k_cols(BatchArgs a) {
-    using g = Geo<N>;
-    __shared__ cf lds[g::CB * Lds<N>::LINE];
-    __shared__ double red[g::NT_COL / kWave];
-    const int slot = blockIdx.x / g::GC, cb = blockIdx.x % g::GC;
+// Columns cb*CB .. of slot `slot`: 1D FFT, Psi' = sqrt(I_j) sgn(Psi) with
+// the error partial, inverse 1D FFT (unscaled), back to scratch.
+template <int N, int CB>
+__device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds,
+                                           double* red) {
+    using g = ColG<N, CB>;
     const int64_t j = a.order[a.off + slot];
-    const int cl = threadIdx.x % g::CB, t = threadIdx.x / g::CB;
-    const int c = cb * g::CB + cl;
+    const int cl = threadIdx.x % CB, t = threadIdx.x / CB;
+    const int c = cb * CB + cl;
     cf* base = a.scratch + (size_t)slot * N * N + c;
+    const float* ampb = a.sqrt_i + (size_t)j * N * N + c;
     cf v[g::N1];
+    float amp[g::N1];
 #pragma unroll
     for (int n1 = 0; n1 < g::N1; ++n1) v[n1] = base[(size_t)(g::N2 * n1 + t) * N];
+#pragma unroll
+    for (int mm = 0; mm < g::N1 / g::N2; ++mm)
+#pragma unroll
+        for (int k2 = 0; k2 < g::N2; ++k2)
+            amp[mm * g::N2 + k2] = ampb[(size_t)((t + g::N2 * mm) + g::N1 * k2) * N];
     cf* z = lds + cl * Lds<N>::LINE;
     passA_to_lds<N, -1>(v, z, t, a.tw);
     __syncthreads();
     passB_from_lds<N, -1>(v, z, t);
-    // modulus replacement Psi' = sqrt(I) sgn(Psi), running error
-    const float* amp = a.sqrt_i + (size_t)j * N * N + c;
     float e = 0.f;
 #pragma unroll
-    for (int mm = 0; mm < g::N1 / g::N2; ++mm)
-#pragma unroll
-        for (int k2 = 0; k2 < g::N2; ++k2) {
-            const int row = (t + g::N2 * mm) + g::N1 * k2;
-            const float s = amp[(size_t)row * N];
-            const cf zz = v[mm * g::N2 + k2];
-            const float mag = sqrtf(norm2(zz));
-            const float d = mag - s;
-            e += d * d;
-            const float f = mag > 0.f ? s / mag : 0.f;
-            v[mm * g::N2 + k2] = f * zz;
-        }
+    for (int i = 0; i < g::N1; ++i) {
+        const float s = amp[i];
+        const cf zz = v[i];
+        const float mag = sqrtf(norm2(zz));
+        const float d = mag - s;
+        e += d * d;
+        const float f = mag > 0.f ? s / mag : 0.f;
+        v[i] = f * zz;
+    }
     __syncthreads();
     passBinv_to_lds<N, +1>(v, z, t, a.tw);
     __syncthreads();
     passAinv_from_lds<N, +1>(v, z, t);
 #pragma unroll
     for (int n1 = 0; n1 < g::N1; ++n1) base[(size_t)(g::N2 * n1 + t) * N] = v[n1];
-    const double tot = block_sum<g::NT_COL>((double)e, red);
+    const double tot = block_sum<g::NT>((double)e, red);
     if (threadIdx.x == 0) a.err_part[(a.off + slot) * g::GC + cb] = tot;
 }
 
 // ---------------------------------------------------------------- stage 3
-template <int N>
-__global__ __launch_bounds__(Geo<N>::NT_ROW) void k_rows_inv(BatchArgs a) {
-    using g = Geo<N>;
-    __shared__ cf lds[g::RB * Lds<N>::LINE];
-    __shared__ float red[g::NT_ROW / kWave];
-    const int slot = blockIdx.x / g::G, rb = blockIdx.x % g::G;
-    const int64_t j = a.order[a.off + slot];
-    const int2 p0 = a.pos[j];
-    const int t = threadIdx.x % g::T, rl = threadIdx.x / g::T;
-    const int r = rb * g::RB + rl;
-    // max |P|^2 over the probe blocks, max |S_j O|^2 over the row blocks
-    float pm = 0.f;
-    for (int i = threadIdx.x; i < a.npmax; i += g::NT_ROW) pm = fmaxf(pm, a.pmax_part[i]);
-    pm = block_max<g::NT_ROW>(pm, red);
-    float om = 0.f;
-    for (int i = threadIdx.x; i < g::G; i += g::NT_ROW) om = fmaxf(om, a.winmax[slot * g::G + i]);
-    om = block_max<g::NT_ROW>(om, red);
-    const float ostep = a.alpha / pm;
-    const float pstep = 1.f / om;
-
-    const cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
-    cf v[g::N1];
+// Probe rows rb*R .. rb*R+R-1, for every slot of the batch (S at a time):
+// inverse 1D FFT of the slot's spectrum row, Delta = psi'/N^2 - P S_j O,
+// object step alpha conj(P) Delta / max|P|^2, probe increment
+// conj(S_j O) Delta / max|S_j O|^2 summed over slots in slot order, then
+// P_{b+1} written for the block.  bsize == 0 only refreshes the block's
+// max |P|^2.
+template <int N, int R, int S>
+__device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl,
+                                               float* red) {
+    using g = InvG<N, R, S>;
+    const int t = threadIdx.x % g::T;
+    const int rl = (threadIdx.x / g::T) % g::R;
+    const int sl = threadIdx.x / (g::T * g::R);
+    const int r = rb * g::R + rl;
+    // the element this thread owns in the probe block (if any)
+    const bool owner = threadIdx.x < g::R * N;
+    const int own_rl = owner ? threadIdx.x / N : 0, own_c = threadIdx.x % N;
+    const size_t own = (size_t)(rb * g::R + own_rl) * N + own_c;
+    const cf p_own = owner ? a.probe[own] : cf{0.f, 0.f};
+    cf acc = cf{0.f, 0.f};
+    if (a.bsize > 0) {
+        const cf* prow = a.probe + (size_t)r * N;
+        cf p[g::N1];
 #pragma unroll
-    for (int mm = 0; mm < g::N1 / g::N2; ++mm)
+        for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = prow[g::N2 * n1 + t];
+        float pm = 0.f;
+        for (int i = threadIdx.x; i < a.npmax; i += g::NT) pm = fmaxf(pm, a.pmax_part[i]);
+        pm = block_max<g::NT>(pm, red);
+        const float ostep = a.alpha / pm;
+        cf* z = lds + (sl * g::R + rl) * Lds<N>::LINE;
+        cf* drow = dl + (sl * g::R + rl) * N;
+        for (int g0 = 0; g0 < a.bsize; g0 += g::S) {
+            const int slot = g0 + sl;
+            const bool act = slot < a.bsize;
+            cf v[g::N1], o[g::N1];
+            cf* orow = nullptr;
+            float om = 1.f;
+            if (act) {
+                const int2 p0 = a.pos[a.order[a.off + slot]];
+                const cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
+                orow = a.obj + (size_t)(p0.x + r) * a.w + p0.y;
 #pragma unroll
-        for (int k2 = 0; k2 < g::N2; ++k2) v[mm * g::N2 + k2] = srow[(t + g::N2 * mm) + g::N1 * k2];
-    cf* z = lds + rl * Lds<N>::LINE;
-    passBinv_to_lds<N, +1>(v, z, t, a.tw);
-    __syncthreads();
-    passAinv_from_lds<N, +1>(v, z, t);
-    constexpr float inv = 1.0f / (float)(N * N);
-    cf* orow = a.obj + (size_t)(p0.x + r) * a.w + p0.y;
-    const cf* prow = a.probe + (size_t)r * N;
-    cf* drow = a.dprobe + (size_t)slot * N * N + (size_t)r * N;
+                for (int mm = 0; mm < g::N1 / g::N2; ++mm)
 #pragma unroll
-    for (int n1 = 0; n1 < g::N1; ++n1) {
-        const int col = g::N2 * n1 + t;
-        const cf o = orow[col];
-        const cf p = prow[col];
-        const cf delta = inv * v[n1] - cmul(p, o);
-        orow[col] = o + ostep * cmulc(p, delta);
-        drow[col] = pstep * cmulc(o, delta);
-    }
-}
-
-// ---------------------------------------------------------------- stage 4
-template <int N>
-__global__ __launch_bounds__(Geo<N>::NT_PROBE) void k_probe(BatchArgs a) {
-    using g = Geo<N>;
-    __shared__ float red[g::NT_PROBE / kWave];
-    const int e = blockIdx.x * g::NT_PROBE + threadIdx.x;
-    float m = 0.f;
-    if (e < N * N) {
-        cf p = a.probe[e];
-        if (a.bsize > 0) {
-            cf acc = a.dprobe[e];
-            for (int s = 1; s < a.bsize; ++s) acc = acc + a.dprobe[(size_t)s * N * N + e];
-            p = p + (a.beta / (float)a.bsize) * acc;
-            a.probe[e] = p;
+                    for (int k2 = 0; k2 < g::N2; ++k2)
+                        v[mm * g::N2 + k2] = srow[(t + g::N2 * mm) + g::N1 * k2];
+#pragma unroll
+                for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = orow[g::N2 * n1 + t];
+                om = 0.f;
+                for (int i = 0; i < a.row_blocks; ++i) om = fmaxf(om, a.winmax[slot * a.row_blocks + i]);
+            } else {
+#pragma unroll
+                for (int n1 = 0; n1 < g::N1; ++n1) {
+                    v[n1] = cf{0.f, 0.f};
+                    o[n1] = cf{0.f, 0.f};
+                }
+            }
+            passBinv_to_lds<N, +1>(v, z, t, a.tw);
+            __syncthreads();
+            passAinv_from_lds<N, +1>(v, z, t);
+            constexpr float inv = 1.0f / (float)(N * N);
+            const float pstep = 1.f / om;
+            if (act) {
+#pragma unroll
+                for (int n1 = 0; n1 < g::N1; ++n1) {
+                    const int col = g::N2 * n1 + t;
+                    const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
+                    orow[col] = o[n1] + ostep * cmulc(p[n1], delta);
+                    drow[col] = pstep * cmulc(o[n1], delta);
+                }
+            }
+            __syncthreads();
+            // slot order: this group's slots ascending, after the earlier groups
+            const int nact = min(g::S, a.bsize - g0);
+            if (owner)
+                for (int q = 0; q < nact; ++q) acc = acc + dl[(q * g::R + own_rl) * N + own_c];
+            __syncthreads();
         }
-        m = norm2(p);
     }
-    m = block_max<g::NT_PROBE>(m, red);
-    if (threadIdx.x == 0) a.pmax_part[blockIdx.x] = m;
+    cf pn = p_own;
+    if (a.bsize > 0 && owner) {
+        pn = p_own + (a.beta / (float)a.bsize) * acc;
+        a.probe[own] = pn;
+    }
+    const float m = block_max<g::NT>(norm2(pn), red);
+    if (threadIdx.x == 0) a.pmax_part[rb] = m;
 }
+
+// ---------------------------------------------------------------- per-batch launches
+template <int N> constexpr int kRowNT = RowG<N, Tile<N>::RB>::NT;
+template <int N> constexpr int kColNT = ColG<N, Tile<N>::CB>::NT;
+template <int N> constexpr int kSweepNT = RowG<N, PTile<N>::B>::NT;
+
+template <int N>
+__global__ __launch_bounds__(kRowNT<N>) void k_rows_fwd(BatchArgs a) {
+    constexpr int RB = Tile<N>::RB;
+    using g = RowG<N, RB>;
+    __shared__ cf lds[RB * Lds<N>::LINE];
+    __shared__ float red[g::NT / kWave];
+    stage_rows_fwd<N, RB>(a, blockIdx.x / g::G, blockIdx.x % g::G, lds, red);
+}
+
+template <int N>
+__global__ __launch_bounds__(kColNT<N>) void k_cols(BatchArgs a) {
+    constexpr int CB = Tile<N>::CB;
+    using g = ColG<N, CB>;
+    __shared__ cf lds[CB * Lds<N>::LINE];
+    __shared__ double red[g::NT / kWave];
+    stage_cols<N, CB>(a, blockIdx.x / g::GC, blockIdx.x % g::GC, lds, red);
+}
+
+template <int N, int R = ITile<N>::R, int S = ITile<N>::S>
+__global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
+    using g = InvG<N, R, S>;
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
+    __shared__ cf dl[g::S * g::R * N];
+    __shared__ float red[g::NT / kWave];
+    stage_rows_inv<N, g::R, g::S>(a, blockIdx.x, lds, dl, red);
+}
+
+// ---------------------------------------------------------------- persistent sweep
+// One cooperative launch runs every batch of a sweep.  Stages are separated
+// by grid-wide barriers: a monotone arrival counter at agent scope (release
+// before the arrival, acquire after the wait).  Every wait is bounded; on
+// expiry the fault flag is raised and all workgroups leave, so the grid
+// always drains.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ inline bool grid_barrier(const SweepCtl& c, unsigned epoch, int* ok_sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = epoch * c.nblocks;
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 1023u) == 0u &&
+                (spins > kSpinLimit || __hip_atomic_load(c.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                __hip_atomic_store(c.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *ok_sh = ok;
+    }
+    __syncthreads();
+    return *ok_sh != 0;
+}
+
+template <int N>
+__global__ __launch_bounds__(kSweepNT<N>) void k_sweep(BatchArgs a, SweepCtl c) {
+    constexpr int TB = PTile<N>::B;
+    using rg = RowG<N, TB>;
+    using cg = ColG<N, TB>;
+    using ig = InvG<N, PTile<N>::R, PTile<N>::S>;
+    static_assert(rg::NT == cg::NT && rg::NT == ig::NT, "one workgroup size for every stage");
+    constexpr int NT = rg::NT;
+    constexpr int LINES = TB > ig::S * ig::R ? TB : ig::S * ig::R;
+    __shared__ cf lds[LINES * Lds<N>::LINE];
+    __shared__ cf dl[ig::S * ig::R * N];
+    __shared__ double redd[NT / kWave];
+    __shared__ float redf[NT / kWave];
+    __shared__ int ok_sh;
+    unsigned epoch = 0;
+    for (int b = 0; b < c.nb; ++b) {
+        const int64_t off = c.offs[b];
+        const int bs = (int)(c.offs[b + 1] - off);
+        if (bs <= 0) continue;
+        a.off = off;
+        a.bsize = bs;
+        for (int it = blockIdx.x; it < bs * rg::G; it += gridDim.x)
+            stage_rows_fwd<N, TB>(a, it / rg::G, it % rg::G, lds, redf);
+        if (!grid_barrier(c, ++epoch, &ok_sh)) return;
+        for (int it = blockIdx.x; it < bs * cg::GC; it += gridDim.x)
+            stage_cols<N, TB>(a, it / cg::GC, it % cg::GC, lds, redd);
+        if (!grid_barrier(c, ++epoch, &ok_sh)) return;
+        for (int it = blockIdx.x; it < ig::GI; it += gridDim.x)
+            stage_rows_inv<N, ig::R, ig::S>(a, it, lds, dl, redf);
+        if (!grid_barrier(c, ++epoch, &ok_sh)) return;
+    }
+}
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 // ---------------------------------------------------------------- ingest
 template <int N>
@@ -265,28 +455,70 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
     for (int64_t i = threadIdx.x; i < n_part; i += 256) num += err_part[i];
     for (int64_t i = threadIdx.x; i < order_len; i += 256) den += sum_i[order[i]];
     num = block_sum<256>(num, red);
-    __syncthreads();
     den = block_sum<256>(den, red);
     if (threadIdx.x == 0) *out = den > 0.0 ? num / den : 0.0;
 }
 
+// ---------------------------------------------------------------- host side
+template <int N>
+Shape shape_n(int form) {
+    if (form == kFormPersistent) {
+        constexpr int TB = PTile<N>::B;
+        return Shape{N / TB, N / TB, InvG<N, PTile<N>::R, PTile<N>::S>::GI};
+    }
+    return Shape{N / Tile<N>::RB, N / Tile<N>::CB, InvG<N>::GI};
+}
+
 template <int N>
 hipError_t batch_n(const BatchArgs& a, hipStream_t s) {
-    using g = Geo<N>;
+    using rg = RowG<N, Tile<N>::RB>;
+    using cg = ColG<N, Tile<N>::CB>;
     if (a.bsize > 0) {
-        hipLaunchKernelGGL(k_rows_fwd<N>, dim3(g::G * a.bsize), dim3(g::NT_ROW), 0, s, a);
-        hipLaunchKernelGGL(k_cols<N>, dim3(g::GC * a.bsize), dim3(g::NT_COL), 0, s, a);
-        hipLaunchKernelGGL(k_rows_inv<N>, dim3(g::G * a.bsize), dim3(g::NT_ROW), 0, s, a);
+        hipLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
+        hipLaunchKernelGGL(k_cols<N>, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
     }
-    hipLaunchKernelGGL(k_probe<N>, dim3(g::PB), dim3(g::NT_PROBE), 0, s, a);
+    hipLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// refresh the partial maxima of |P|^2 in the layout of `form`
+template <int N>
+hipError_t probe_n(const BatchArgs& a, int form, hipStream_t s) {
+    BatchArgs z = a;
+    z.bsize = 0;
+    if (form == kFormPersistent) {
+        constexpr int R = PTile<N>::R, S = PTile<N>::S;
+        using g = InvG<N, R, S>;
+        k_rows_inv<N, R, S><<<dim3(g::GI), dim3(g::NT), 0, s>>>(z);
+    } else {
+        hipLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, z);
+    }
     return hipGetLastError();
 }
 
 template <int N>
-hipError_t probe_n(const BatchArgs& a, hipStream_t s) {
-    using g = Geo<N>;
-    hipLaunchKernelGGL(k_probe<N>, dim3(g::PB), dim3(g::NT_PROBE), 0, s, a);
-    return hipGetLastError();
+int persistent_capacity_n() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_sweep<N>),
+                                                     kSweepNT<N>, 0) != hipSuccess)
+        return 0;
+    return per * cus;
+}
+
+template <int N>
+hipError_t sweep_n(const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s) {
+    constexpr int TB = PTile<N>::B;
+    const int need = std::max(max_batch * (N / TB), InvG<N, PTile<N>::R, PTile<N>::S>::GI);
+    const int grid = std::min(need, (int)c.nblocks);
+    SweepCtl cc = c;
+    cc.nblocks = (unsigned)grid;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, cc.bar);
+    BatchArgs aa = a;
+    void* args[] = {&aa, &cc};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sweep<N>), dim3(grid), dim3(kSweepNT<N>),
+                                      args, 0, s);
 }
 
 template <int N>
@@ -298,58 +530,47 @@ hipError_t ingest_n(const float* src, float* dst, double* sum_i, int64_t count, 
     return hipGetLastError();
 }
 
-template <int N>
-Shape shape_n() {
-    using g = Geo<N>;
-    return Shape{g::G, g::GC, g::PB};
-}
-
 }  // namespace
+
+#define PTYC_DISPATCH(n, call)                             \
+    switch (n) {                                           \
+        case 16: { constexpr int N = 16; return call; }   \
+        case 32: { constexpr int N = 32; return call; }   \
+        case 64: { constexpr int N = 64; return call; }   \
+        case 128: { constexpr int N = 128; return call; } \
+        case 256: { constexpr int N = 256; return call; } \
+    }
 
 bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
-Shape shape_for(int n) {
-    switch (n) {
-        case 16: return shape_n<16>();
-        case 32: return shape_n<32>();
-        case 64: return shape_n<64>();
-        case 128: return shape_n<128>();
-        case 256: return shape_n<256>();
-    }
+Shape shape_for(int n, int form) {
+    PTYC_DISPATCH(n, shape_n<N>(form));
     return Shape{0, 0, 0};
 }
 
 hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s) {
-    switch (n) {
-        case 16: return batch_n<16>(a, s);
-        case 32: return batch_n<32>(a, s);
-        case 64: return batch_n<64>(a, s);
-        case 128: return batch_n<128>(a, s);
-        case 256: return batch_n<256>(a, s);
-    }
+    PTYC_DISPATCH(n, batch_n<N>(a, s));
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_probe_reduce(int n, const BatchArgs& a, hipStream_t s) {
-    switch (n) {
-        case 16: return probe_n<16>(a, s);
-        case 32: return probe_n<32>(a, s);
-        case 64: return probe_n<64>(a, s);
-        case 128: return probe_n<128>(a, s);
-        case 256: return probe_n<256>(a, s);
-    }
+hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s) {
+    PTYC_DISPATCH(n, probe_n<N>(a, form, s));
+    return hipErrorInvalidValue;
+}
+
+int persistent_capacity(int n) {
+    PTYC_DISPATCH(n, persistent_capacity_n<N>());
+    return 0;
+}
+
+hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s) {
+    PTYC_DISPATCH(n, sweep_n<N>(a, c, max_batch, s));
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_ingest(int n, const float* src, float* dst, double* sum_i, int64_t count,
                          bool is_sqrt, bool centred, int* bad, hipStream_t s) {
-    switch (n) {
-        case 16: return ingest_n<16>(src, dst, sum_i, count, is_sqrt, centred, bad, s);
-        case 32: return ingest_n<32>(src, dst, sum_i, count, is_sqrt, centred, bad, s);
-        case 64: return ingest_n<64>(src, dst, sum_i, count, is_sqrt, centred, bad, s);
-        case 128: return ingest_n<128>(src, dst, sum_i, count, is_sqrt, centred, bad, s);
-        case 256: return ingest_n<256>(src, dst, sum_i, count, is_sqrt, centred, bad, s);
-    }
+    PTYC_DISPATCH(n, ingest_n<N>(src, dst, sum_i, count, is_sqrt, centred, bad, s));
     return hipErrorInvalidValue;
 }
 

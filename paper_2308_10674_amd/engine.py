@@ -62,7 +62,7 @@ class Engine:
     """
 
     def __init__(self, n, h, w, probe0, object0, *, alpha=1.0, beta=1.0, mode="coloured",
-                 max_batch=0, seed=0, sqrt_input=False, centred=False, stream=None):
+                 max_batch=0, seed=0, sqrt_input=False, centred=False, stream=None, form="default"):
         lib = L.lib()
         cfg = L.Config(n=n, h=h, w=w, alpha=alpha, beta=beta,
                        mode=L.PTYC_MODE_STRICT if mode == "strict" else L.PTYC_MODE_COLOURED,
@@ -79,6 +79,8 @@ class Engine:
         self._ctx = C.c_void_p()
         self.n, self.h, self.w, self.mode = n, h, w, mode
         _check(lib.ptyc_init(C.byref(self._ctx), C.byref(cfg), pp, op, pk, stream))
+        if form != "default":
+            self.form = form
 
     # ------------------------------------------------------------------ data
     def add_positions(self, positions, intensities):
@@ -154,6 +156,17 @@ class Engine:
     def set_probe(self, probe):
         p, k, keep = _buffer(probe, np.complex64, torch.complex64 if torch is not None else None)
         _check(L.lib().ptyc_set_probe(self._ctx, p, k), self._ctx)
+
+    @property
+    def form(self) -> str:
+        f = int(L.lib().ptyc_get_form(self._ctx))
+        return {L.PTYC_FORM_BATCH: "batch", L.PTYC_FORM_PERSISTENT: "persistent"}.get(f, str(f))
+
+    @form.setter
+    def form(self, name):
+        code = {"default": L.PTYC_FORM_DEFAULT, "batch": L.PTYC_FORM_BATCH,
+                "persistent": L.PTYC_FORM_PERSISTENT}[name]
+        _check(L.lib().ptyc_set_form(self._ctx, code), self._ctx)
 
     @property
     def num_positions(self) -> int:

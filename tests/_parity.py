@@ -10,12 +10,12 @@ import sim
 RTOL = 1e-5   # relative L2 per re-synced sweep (FP32 GPU against the FP64 oracle)
 
 
-def engine_for(wl, mode=None, max_batch=0, seed=None, count=None, alpha=None, beta=None):
+def engine_for(wl, mode=None, max_batch=0, seed=None, count=None, alpha=None, beta=None, form="default"):
     from paper_2308_10674_amd import Engine
     mode = mode or ("strict" if wl.mode == "strict" else "coloured")
     eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0,
                  alpha=wl.alpha if alpha is None else alpha, beta=wl.beta if beta is None else beta,
-                 mode=mode, max_batch=max_batch, seed=wl.seed if seed is None else seed)
+                 mode=mode, max_batch=max_batch, seed=wl.seed if seed is None else seed, form=form)
     count = wl.count if count is None else count
     if count:
         eng.add_positions(wl.positions[:count], wl.intensities[:count])

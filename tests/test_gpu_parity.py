@@ -78,11 +78,13 @@ def test_config0_every_position():
         O, P, _, _ = oracle.sweep_strict(O, P, wl.positions, wl.intensities, order)
 
 
-def test_coloured_128_every_batch():
+@pytest.mark.parametrize("form", ["persistent", "batch"])
+def test_coloured_128_every_batch(form):
     """128 px, first 600 raster positions: every batch of the library's
-    first two sweeps re-synced."""
+    first two sweeps re-synced, in both launch forms."""
     wl = sim.make_config(1, n_positions=600)
-    eng = engine_for(wl)
+    eng = engine_for(wl, form=form)
+    assert eng.form == form
     O, P = wl.object0, wl.probe0
     for s in range(2):
         order, off = eng.get_schedule()
@@ -91,13 +93,14 @@ def test_coloured_128_every_batch():
         eng.sweep(1, order=order, batch_offsets=off)     # advance the sweep counter
 
 
-def test_coloured_256_every_batch():
+@pytest.mark.parametrize("form", ["persistent", "batch"])
+def test_coloured_256_every_batch(form):
     """256 px on the 2048^2 object (every 30th spiral position): every batch
-    of the first sweep re-synced."""
+    of the first sweep re-synced, in both launch forms."""
     c = sim.CONFIGS[2]
     pos = sim.fermat_positions(20000, 6.0, 256, 2048)[::30]
     wl = sim.make_workload(256, 2048, c["radius"], c["kappa"], pos, c["photons"], 1002, config=2)
-    eng = engine_for(wl)
+    eng = engine_for(wl, form=form)
     order, off = eng.get_schedule()
     rows, _ = run_batches_resynced(eng, wl, order, off, label="cfg2 s0")
     check_batches(rows)
@@ -240,6 +243,19 @@ def test_max_batch_cap_and_explicit_batches():
 
 
 # ------------------------------------------------------------------ bit-level properties
+
+@pytest.mark.parametrize("cfg,count,mode", [(1, 600, "coloured"), (0, 100, "strict"), (2, 400, "coloured")])
+def test_launch_forms_agree_bitwise(cfg, count, mode):
+    """The persistent sweep kernel and the per-batch launches perform the same
+    per-element arithmetic: identical object and probe bytes."""
+    wl = sim.make_config(cfg, n_positions=count)
+    a = engine_for(wl, mode=mode, form="persistent")
+    b = engine_for(wl, mode=mode, form="batch")
+    ea = a.sweep(2, errors=True)
+    eb = b.sweep(2, errors=True)
+    np.testing.assert_array_equal(a.get_object(), b.get_object())
+    np.testing.assert_array_equal(a.get_probe(), b.get_probe())
+    np.testing.assert_allclose(ea, eb, rtol=1e-12)
 
 def test_default_schedule_matches_exported_and_is_deterministic():
     wl = sim.make_config(1, n_positions=400)
