@@ -174,6 +174,26 @@ const char* ptyc_last_error(const ptyc_ctx* ctx);
 /* Text of the last error of a failed ptyc_init on this thread. */
 const char* ptyc_init_error(void);
 
+/* Amplitude loss and its gradient, for gradient-based reconstruction beside
+ * ePIE (not in the paper; the same forward model F(P * S_j O)):
+ *   L = sum_{j in idx} sum_k (|F(P * S_j O)|_k - sqrt(I_j,k))^2
+ * obj (H*W) and probe (N*N): device complex64 buffers holding the current
+ * estimate (the context's own object and probe are not used or changed);
+ * idx: host array of `count` loaded position indices (a minibatch; windows
+ * may overlap); loss_out: host double receiving L.  If grad_obj and
+ * grad_probe (device complex64, H*W and N*N) are given they are overwritten
+ * with grad_scale * dL/dO and grad_scale * dL/dP in PyTorch's convention
+ * for real functions of complex variables (dL/dRe + i dL/dIm):
+ *   g_Psi = 2 (|Psi| - sqrt I) sgn(Psi), g_psi = F^H g_Psi,
+ *   dL/dO[window j] += conj(P) g_psi,  dL/dP += conj(S_j O) g_psi.
+ * Overlapping windows are accumulated in a fixed order (the minibatch is
+ * split into batches of disjoint windows), so the result is deterministic.
+ * Synchronises the stream.  Errors: PTYC_ERR_ARG for NULL buffers, an
+ * index that is not loaded, only one gradient buffer, a non-finite scale. */
+int ptyc_amp_loss(ptyc_ctx* ctx, const void* obj, const void* probe, const int64_t* idx,
+                  int64_t count, float grad_scale, void* grad_obj, void* grad_probe,
+                  double* loss_out);
+
 /* ---- host-only helpers (no device needed) ---- */
 
 /* Greedy first-fit colouring of window corners in index order: position j

@@ -52,6 +52,7 @@ SIGNATURES = {
     "ptyc_get_probe": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_set_object": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_set_probe": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_amp_loss": (C.c_int, [_P, _P, _P, _I64P, C.c_int64, C.c_float, _P, _P, _DP]),
     "ptyc_set_form": (C.c_int, [_P, C.c_int]),
     "ptyc_get_form": (C.c_int, [_P]),
     "ptyc_num_positions": (C.c_int64, [_P]),

@@ -574,6 +574,79 @@ int ptyc_set_probe(ptyc_ctx* c, const void* in, int kind) {
     return refresh_probe_max(c);
 }
 
+int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,
+                  float grad_scale, void* grad_obj, void* grad_probe, double* loss_out) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!obj || !probe || !loss_out) return fail(c, PTYC_ERR_ARG, "obj, probe and loss_out must not be NULL");
+    if ((grad_obj == nullptr) != (grad_probe == nullptr))
+        return fail(c, PTYC_ERR_ARG, "grad_obj and grad_probe must both be given or both be NULL");
+    if (count < 0 || (count > 0 && !idx)) return fail(c, PTYC_ERR_ARG, "bad index list");
+    if (!std::isfinite(grad_scale)) return fail(c, PTYC_ERR_ARG, "grad_scale must be finite");
+    for (int64_t i = 0; i < count; ++i)
+        if (idx[i] < 0 || idx[i] >= c->n_loaded)
+            return fail(c, PTYC_ERR_ARG, "index " + std::to_string(idx[i]) + " is not a loaded position");
+    const bool grad = grad_obj != nullptr;
+    const int n = c->cfg.n;
+    const size_t nn = (size_t)n * n;
+    if (grad) {
+        HIPCHK(c, launch_fill_zero(grad_obj, (int64_t)c->cfg.h * c->cfg.w, c->stream));
+        HIPCHK(c, launch_fill_zero(grad_probe, (int64_t)nn, c->stream));
+    }
+    if (count == 0) {
+        *loss_out = 0.0;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return PTYC_OK;
+    }
+    // batches of disjoint windows inside the minibatch (greedy, in list order)
+    std::vector<int32_t> mp((size_t)(2 * count));
+    for (int64_t i = 0; i < count; ++i) {
+        mp[(size_t)(2 * i)] = c->h_pos[(size_t)(2 * idx[i])];
+        mp[(size_t)(2 * i + 1)] = c->h_pos[(size_t)(2 * idx[i] + 1)];
+    }
+    Colouring col(n, max_batch_of(c));
+    col.extend(mp.data(), 0, count);
+    std::vector<int64_t> order, off{0};
+    for (const auto& m : col.members()) {
+        for (int64_t k : m) order.push_back(idx[k]);
+        off.push_back((int64_t)order.size());
+    }
+    int64_t max_b = 1;
+    for (size_t b = 0; b + 1 < off.size(); ++b) max_b = std::max(max_b, off[b + 1] - off[b]);
+    if (max_b > c->slots) {
+        if ((rc = ensure(c, c->scratch, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->dprobe, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->winmax, (size_t)max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
+        c->slots = max_b;
+    }
+    const size_t obytes = (size_t)count * sizeof(int64_t);
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    if ((rc = ensure(c, c->order, obytes)) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_part, (size_t)count * c->sb.col_blocks * sizeof(double))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_dev, sizeof(double))) != PTYC_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->order.p, order.data(), obytes, hipMemcpyHostToDevice, c->stream));
+    BatchArgs a = base_args(c);
+    a.row_blocks = c->sb.row_blocks;
+    a.obj = (cf*)obj;
+    a.probe = (cf*)probe;
+    a.gobj = (cf*)grad_obj;
+    a.gprobe = (cf*)grad_probe;
+    a.gscale = grad_scale;
+    for (size_t b = 0; b + 1 < off.size(); ++b) {
+        a.off = off[b];
+        a.bsize = (int)(off[b + 1] - off[b]);
+        HIPCHK(c, launch_loss(n, a, grad, c->stream));
+    }
+    HIPCHK(c, launch_sum_reduce((const double*)c->err_part.p, count * c->sb.col_blocks, (double*)c->err_dev.p,
+                                c->stream));
+    HIPCHK(c, hipMemcpyAsync(loss_out, c->err_dev.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
 int ptyc_colour(int64_t count, const int32_t* pos_yx, int32_t n, int32_t max_batch, int32_t* colour_out,
                 int32_t* n_colours) {
     if (count < 0 || n <= 0 || max_batch < 0 || (count > 0 && (!pos_yx || !colour_out)) || !n_colours)

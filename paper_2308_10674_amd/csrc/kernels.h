@@ -27,7 +27,13 @@ struct BatchArgs {
     int npmax;                // number of probe row blocks
     double* err_part;         // [order_len][column blocks] error partial sums
     float alpha, beta;
+    cf* gobj;                 // amplitude-loss gradient w.r.t. the object (accumulated)
+    cf* gprobe;               // amplitude-loss gradient w.r.t. the probe (accumulated)
+    float gscale;             // upstream scale of the gradient
 };
+
+// What the column and inverse-row stages compute.
+enum : int { kModeEpie = 0, kModeGrad = 1, kModeLoss = 2 };
 
 // Launch forms of a sweep.
 enum : int { kFormBatch = 1, kFormPersistent = 2 };
@@ -56,6 +62,11 @@ hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s);
 hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel
 hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s);
+// amplitude loss over one batch of disjoint windows; grad: also accumulate
+// dL/dO into gobj and dL/dP into gprobe
+hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s);
+hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hipStream_t s);
 hipError_t launch_ingest(int n, const float* src, float* sqrt_i_dst, double* sum_i_dst,
                          int64_t count, bool is_sqrt, bool centred, int* bad_flag,
                          hipStream_t s);

@@ -187,7 +187,7 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
 // ---------------------------------------------------------------- stage 2
 // Columns cb*CB .. of slot `slot`: 1D FFT, Psi' = sqrt(I_j) sgn(Psi) with
 // the error partial, inverse 1D FFT (unscaled), back to scratch.
-template <int N, int CB>
+template <int N, int CB, int MODE = kModeEpie>
 __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds,
                                            double* red) {
     using g = ColG<N, CB>;
@@ -217,15 +217,24 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
         const float mag = sqrtf(norm2(zz));
         const float d = mag - s;
         e += d * d;
-        const float f = mag > 0.f ? s / mag : 0.f;
-        v[i] = f * zz;
+        if (MODE == kModeEpie) {
+            // Psi' = sqrt(I) sgn(Psi)
+            const float f = mag > 0.f ? s / mag : 0.f;
+            v[i] = f * zz;
+        } else if (MODE == kModeGrad) {
+            // dL/dPsi (PyTorch convention) = 2 (|Psi| - sqrt(I)) sgn(Psi), times the upstream scale
+            const float f = mag > 0.f ? (2.f * a.gscale) * (d / mag) : 0.f;
+            v[i] = f * zz;
+        }
     }
-    __syncthreads();
-    passBinv_to_lds<N, +1>(v, z, t, a.tw);
-    __syncthreads();
-    passAinv_from_lds<N, +1>(v, z, t);
+    if (MODE != kModeLoss) {
+        __syncthreads();
+        passBinv_to_lds<N, +1>(v, z, t, a.tw);
+        __syncthreads();
+        passAinv_from_lds<N, +1>(v, z, t);
 #pragma unroll
-    for (int n1 = 0; n1 < g::N1; ++n1) base[(size_t)(g::N2 * n1 + t) * N] = v[n1];
+        for (int n1 = 0; n1 < g::N1; ++n1) base[(size_t)(g::N2 * n1 + t) * N] = v[n1];
+    }
     const double tot = block_sum<g::NT>((double)e, red);
     if (threadIdx.x == 0) a.err_part[(a.off + slot) * g::GC + cb] = tot;
 }
@@ -237,7 +246,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 // conj(S_j O) Delta / max|S_j O|^2 summed over slots in slot order, then
 // P_{b+1} written for the block.  bsize == 0 only refreshes the block's
 // max |P|^2.
-template <int N, int R, int S>
+template <int N, int R, int S, int MODE = kModeEpie>
 __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl,
                                                float* red) {
     using g = InvG<N, R, S>;
@@ -249,17 +258,20 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     const bool owner = threadIdx.x < g::R * N;
     const int own_rl = owner ? threadIdx.x / N : 0, own_c = threadIdx.x % N;
     const size_t own = (size_t)(rb * g::R + own_rl) * N + own_c;
-    const cf p_own = owner ? a.probe[own] : cf{0.f, 0.f};
+    const cf p_own = owner ? (MODE == kModeEpie ? a.probe[own] : a.gprobe[own]) : cf{0.f, 0.f};
     cf acc = cf{0.f, 0.f};
     if (a.bsize > 0) {
         const cf* prow = a.probe + (size_t)r * N;
         cf p[g::N1];
 #pragma unroll
         for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = prow[g::N2 * n1 + t];
-        float pm = 0.f;
-        for (int i = threadIdx.x; i < a.npmax; i += g::NT) pm = fmaxf(pm, a.pmax_part[i]);
-        pm = block_max<g::NT>(pm, red);
-        const float ostep = a.alpha / pm;
+        float ostep = 0.f;
+        if (MODE == kModeEpie) {
+            float pm = 0.f;
+            for (int i = threadIdx.x; i < a.npmax; i += g::NT) pm = fmaxf(pm, a.pmax_part[i]);
+            pm = block_max<g::NT>(pm, red);
+            ostep = a.alpha / pm;
+        }
         cf* z = lds + (sl * g::R + rl) * Lds<N>::LINE;
         cf* drow = dl + (sl * g::R + rl) * N;
         for (int g0 = 0; g0 < a.bsize; g0 += g::S) {
@@ -279,8 +291,10 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                         v[mm * g::N2 + k2] = srow[(t + g::N2 * mm) + g::N1 * k2];
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = orow[g::N2 * n1 + t];
-                om = 0.f;
-                for (int i = 0; i < a.row_blocks; ++i) om = fmaxf(om, a.winmax[slot * a.row_blocks + i]);
+                if (MODE == kModeEpie) {
+                    om = 0.f;
+                    for (int i = 0; i < a.row_blocks; ++i) om = fmaxf(om, a.winmax[slot * a.row_blocks + i]);
+                }
             } else {
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
@@ -293,13 +307,23 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             passAinv_from_lds<N, +1>(v, z, t);
             constexpr float inv = 1.0f / (float)(N * N);
             const float pstep = 1.f / om;
-            if (act) {
+            if (act && MODE == kModeEpie) {
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     const int col = g::N2 * n1 + t;
                     const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
                     orow[col] = o[n1] + ostep * cmulc(p[n1], delta);
                     drow[col] = pstep * cmulc(o[n1], delta);
+                }
+            } else if (act) {
+                // v = F^H g_Psi = dL/dpsi: dL/dO on the window += conj(P) g, dL/dP += conj(S_j O) g
+                const int2 p0 = a.pos[a.order[a.off + slot]];
+                cf* grow = a.gobj + (size_t)(p0.x + r) * a.w + p0.y;
+#pragma unroll
+                for (int n1 = 0; n1 < g::N1; ++n1) {
+                    const int col = g::N2 * n1 + t;
+                    grow[col] = grow[col] + cmulc(p[n1], v[n1]);
+                    drow[col] = cmulc(o[n1], v[n1]);
                 }
             }
             __syncthreads();
@@ -310,13 +334,17 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             __syncthreads();
         }
     }
-    cf pn = p_own;
-    if (a.bsize > 0 && owner) {
-        pn = p_own + (a.beta / (float)a.bsize) * acc;
-        a.probe[own] = pn;
+    if (MODE == kModeEpie) {
+        cf pn = p_own;
+        if (a.bsize > 0 && owner) {
+            pn = p_own + (a.beta / (float)a.bsize) * acc;
+            a.probe[own] = pn;
+        }
+        const float m = block_max<g::NT>(norm2(pn), red);
+        if (threadIdx.x == 0) a.pmax_part[rb] = m;
+    } else if (a.bsize > 0 && owner) {
+        a.gprobe[own] = p_own + acc;
     }
-    const float m = block_max<g::NT>(norm2(pn), red);
-    if (threadIdx.x == 0) a.pmax_part[rb] = m;
 }
 
 // ---------------------------------------------------------------- per-batch launches
@@ -349,6 +377,31 @@ __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     __shared__ cf dl[g::S * g::R * N];
     __shared__ float red[g::NT / kWave];
     stage_rows_inv<N, g::R, g::S>(a, blockIdx.x, lds, dl, red);
+}
+
+// Amplitude-loss forward (MODE kModeLoss: rows_fwd + cols only) and its
+// adjoint (kModeGrad: rows_fwd, cols, rows_inv accumulating the gradients).
+template <int N, int MODE>
+__global__ __launch_bounds__(kColNT<N>) void k_cols_mode(BatchArgs a) {
+    constexpr int CB = Tile<N>::CB;
+    using g = ColG<N, CB>;
+    __shared__ cf lds[CB * Lds<N>::LINE];
+    __shared__ double red[g::NT / kWave];
+    stage_cols<N, CB, MODE>(a, blockIdx.x / g::GC, blockIdx.x % g::GC, lds, red);
+}
+
+template <int N, int R = ITile<N>::R, int S = ITile<N>::S>
+__global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_grad(BatchArgs a) {
+    using g = InvG<N, R, S>;
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
+    __shared__ cf dl[g::S * g::R * N];
+    __shared__ float red[g::NT / kWave];
+    stage_rows_inv<N, g::R, g::S, kModeGrad>(a, blockIdx.x, lds, dl, red);
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(cf* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = cf{0.f, 0.f};
 }
 
 // ---------------------------------------------------------------- persistent sweep
@@ -449,14 +502,14 @@ __global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ src, f
 // ---------------------------------------------------------------- error
 __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int64_t n_part,
                                                     const int64_t* order, int64_t order_len,
-                                                    const double* sum_i, double* out) {
+                                                    const double* sum_i, double* out, int raw) {
     __shared__ double red[256 / kWave];
     double num = 0.0, den = 0.0;
     for (int64_t i = threadIdx.x; i < n_part; i += 256) num += err_part[i];
     for (int64_t i = threadIdx.x; i < order_len; i += 256) den += sum_i[order[i]];
     num = block_sum<256>(num, red);
     den = block_sum<256>(den, red);
-    if (threadIdx.x == 0) *out = den > 0.0 ? num / den : 0.0;
+    if (threadIdx.x == 0) *out = raw ? num : (den > 0.0 ? num / den : 0.0);
 }
 
 // ---------------------------------------------------------------- host side
@@ -492,6 +545,21 @@ hipError_t probe_n(const BatchArgs& a, int form, hipStream_t s) {
         k_rows_inv<N, R, S><<<dim3(g::GI), dim3(g::NT), 0, s>>>(z);
     } else {
         hipLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, z);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t loss_n(const BatchArgs& a, bool grad, hipStream_t s) {
+    using rg = RowG<N, Tile<N>::RB>;
+    using cg = ColG<N, Tile<N>::CB>;
+    if (a.bsize <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
+    if (grad) {
+        hipLaunchKernelGGL((k_cols_mode<N, kModeGrad>), dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
+        hipLaunchKernelGGL(k_rows_grad<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_cols_mode<N, kModeLoss>), dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -568,6 +636,24 @@ hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_ba
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s) {
+    PTYC_DISPATCH(n, loss_n<N>(a, grad, s));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s) {
+    if (count_c64 <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count_c64 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (cf*)p, count_c64);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, s, part, n_part, (const int64_t*)nullptr,
+                       (int64_t)0, (const double*)nullptr, out, 1);
+    return hipGetLastError();
+}
+
 hipError_t launch_ingest(int n, const float* src, float* dst, double* sum_i, int64_t count,
                          bool is_sqrt, bool centred, int* bad, hipStream_t s) {
     PTYC_DISPATCH(n, ingest_n<N>(src, dst, sum_i, count, is_sqrt, centred, bad, s));
@@ -578,7 +664,7 @@ hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const int64
                              int64_t order_len, const double* sum_i, double* err_out,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, s, err_part, n_part, order, order_len,
-                       sum_i, err_out);
+                       sum_i, err_out, 0);
     return hipGetLastError();
 }
 

@@ -157,6 +157,29 @@ class Engine:
         p, k, keep = _buffer(probe, np.complex64, torch.complex64 if torch is not None else None)
         _check(L.lib().ptyc_set_probe(self._ctx, p, k), self._ctx)
 
+    # ------------------------------------------------------------ gradient
+    def amp_loss(self, obj, probe, idx, grad=False, scale=1.0):
+        """Amplitude loss sum_j || |F(P S_j O)| - sqrt(I_j) ||^2 over the
+        positions ``idx`` for the device tensors ``obj`` and ``probe``
+        (complex64).  With ``grad`` also returns scale * dL/dO and
+        scale * dL/dP (PyTorch convention) as new device tensors."""
+        o = obj.detach()
+        p = probe.detach()
+        if not (o.is_cuda and p.is_cuda) or o.dtype != torch.complex64 or p.dtype != torch.complex64:
+            raise ValueError("obj and probe must be complex64 CUDA tensors")
+        o = o.contiguous()
+        p = p.contiguous()
+        ia, ip = _i64(np.asarray(idx, dtype=np.int64).ravel())
+        loss = C.c_double()
+        go = gp = None
+        if grad:
+            go = torch.empty_like(o)
+            gp = torch.empty_like(p)
+        _check(L.lib().ptyc_amp_loss(self._ctx, o.data_ptr(), p.data_ptr(), ip, len(ia), float(scale),
+                                     go.data_ptr() if grad else None, gp.data_ptr() if grad else None,
+                                     C.byref(loss)), self._ctx)
+        return (loss.value, go, gp) if grad else loss.value
+
     @property
     def form(self) -> str:
         f = int(L.lib().ptyc_get_form(self._ctx))

@@ -10,6 +10,14 @@ import sim
 RTOL = 1e-5   # relative L2 per re-synced sweep (FP32 GPU against the FP64 oracle)
 
 
+def progress(msg):
+    """A line on the process's real stderr (not captured by pytest), so long
+    tests show that they are alive."""
+    import sys
+    sys.__stderr__.write(msg + "\n")
+    sys.__stderr__.flush()
+
+
 def engine_for(wl, mode=None, max_batch=0, seed=None, count=None, alpha=None, beta=None, form="default"):
     from paper_2308_10674_amd import Engine
     mode = mode or ("strict" if wl.mode == "strict" else "coloured")
@@ -86,6 +94,7 @@ def run_resynced(eng, wl, n_sweeps, schedule, count=None, start=None, label=""):
         if max(row["rel_o"], row["rel_p"], row["rel_err"]) > RTOL:
             row["floor_o"], row["floor_p"], row["floor_err"] = fp32_floor(O, P, wl, order, off, mask, count=count)
         print(label, row, flush=True)
+        progress(f"{label}: sweep {s} compared")
         rows.append(row)
         O, P = On, Pn
     return rows, (O, P)
@@ -139,6 +148,7 @@ def run_batches_resynced(eng, wl, order, off, count=None, start=None, label="", 
             O, P = On, Pn
     worst = max(rows, key=lambda r: max(r["rel_o"], r["rel_p"], r["rel_err"])) if rows else None
     print(label, f"{len(rows)} batches re-synced, worst", worst, flush=True)
+    progress(f"{label}: {len(rows)} batches re-synced")
     return rows, (O, P)
 
 

@@ -1,0 +1,165 @@
+"""Amplitude-loss forward and hand-written adjoint on the GPU (through the
+C ABI) against the FP64 oracle's loss and adjoint; the autograd wrapper."""
+import numpy as np
+import pytest
+
+import oracle
+import sim
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_10674_amd import _lib
+    _lib.lib()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def problem(torch_cuda):
+    """128 px patterns, first 400 positions of the raster, an estimate near
+    the truth (so the Fourier moduli are well above FP32 resolution)."""
+    torch = torch_cuda
+    from paper_2308_10674_amd import Engine
+    wl = sim.make_config(1, n_positions=400)
+    rng = np.random.default_rng(31)
+    O = wl.object_true * np.exp(0.15j * rng.standard_normal(wl.object_true.shape))
+    P = wl.probe_true * (1 + 0.05 * rng.standard_normal(wl.probe_true.shape))
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(wl.positions, wl.intensities)
+    to = torch.from_numpy(O.astype(np.complex64)).cuda()
+    tp = torch.from_numpy(P.astype(np.complex64)).cuda()
+    idx = rng.choice(wl.count, 120, replace=False)
+    return dict(wl=wl, eng=eng, O=O.astype(np.complex64), P=P.astype(np.complex64), to=to, tp=tp, idx=idx)
+
+
+def test_loss_matches_oracle(problem):
+    pr = problem
+    L = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"])
+    Lo = oracle.amplitude_loss(pr["O"].astype(np.complex128), pr["P"].astype(np.complex128),
+                               pr["wl"].positions, pr["wl"].intensities, pr["idx"])
+    assert abs(L - Lo) <= RTOL * Lo, (L, Lo)
+
+
+def test_gradient_matches_cpu_adjoint(problem):
+    pr = problem
+    wl = pr["wl"]
+    L, go, gp = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True)
+    Lo, go_o, gp_o = oracle.amplitude_loss_grad(pr["O"], pr["P"], wl.positions, wl.intensities, pr["idx"])
+    mask = oracle.union_mask(wl.positions[pr["idx"]], wl.n, wl.h, wl.w)
+    go = go.cpu().numpy()
+    gp = gp.cpu().numpy()
+    ro = oracle.rel_l2(go, go_o, mask)
+    rp = oracle.rel_l2(gp, gp_o)
+    print("grad rel-L2 object", ro, "probe", rp)
+    assert ro <= RTOL and rp <= RTOL
+    assert np.all(go[~mask] == 0)
+    assert abs(L - Lo) <= RTOL * Lo
+
+
+def test_gradient_is_deterministic_and_scaled(problem):
+    pr = problem
+    _, a_o, a_p = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True)
+    _, b_o, b_p = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True)
+    _, c_o, c_p = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True, scale=0.5)
+    assert bool((a_o == b_o).all()) and bool((a_p == b_p).all())
+    np.testing.assert_allclose(c_o.cpu().numpy(), 0.5 * a_o.cpu().numpy(), rtol=1e-6, atol=0)
+    np.testing.assert_allclose(c_p.cpu().numpy(), 0.5 * a_p.cpu().numpy(), rtol=1e-6, atol=0)
+
+
+def test_gradient_equals_scaled_epie_step(problem, torch_cuda):
+    """For one position the ePIE object step is -alpha / (2 N^2 max|P|^2)
+    times the loss gradient: two different GPU paths tied by a closed form."""
+    torch = torch_cuda
+    from paper_2308_10674_amd import Engine
+    pr = problem
+    wl = pr["wl"]
+    j = int(pr["idx"][0])
+    _, go, _ = pr["eng"].amp_loss(pr["to"], pr["tp"], [j], grad=True)
+    e = Engine(wl.n, wl.h, wl.w, pr["P"], pr["O"], alpha=0.7, beta=0.0, mode="strict")
+    e.add_positions(wl.positions, wl.intensities)
+    e.sweep(1, order=[j])
+    step = e.get_object().astype(np.complex128) - pr["O"].astype(np.complex128)
+    scale = -0.7 / (2 * wl.n * wl.n * np.max(np.abs(pr["P"].astype(np.complex128)) ** 2))
+    y, x = wl.positions[j]
+    win = (slice(y, y + wl.n), slice(x, x + wl.n))
+    r = oracle.rel_l2(step[win], scale * go.cpu().numpy().astype(np.complex128)[win])
+    assert r <= 1e-4, r   # the step is a small difference of FP32 numbers near 1
+
+
+def test_autograd_function(problem, torch_cuda):
+    torch = torch_cuda
+    from paper_2308_10674_amd import amplitude_loss
+    pr = problem
+    O = pr["to"].clone().requires_grad_(True)
+    P = pr["tp"].clone().requires_grad_(True)
+    loss = amplitude_loss(pr["eng"], O, P, pr["idx"])
+    (3.0 * loss).backward()
+    _, go, gp = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True, scale=3.0)
+    assert bool((O.grad == go).all()) and bool((P.grad == gp).all())
+
+
+def test_directional_derivative(problem, torch_cuda):
+    """Central differences of the GPU loss along random directions agree
+    with Re<grad, V> (checks conjugation and factor conventions)."""
+    torch = torch_cuda
+    pr = problem
+    eng = pr["eng"]
+    L, go, gp = eng.amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    for which in ("O", "P"):
+        base = pr["to"] if which == "O" else pr["tp"]
+        V = torch.complex(torch.randn(base.shape, generator=g), torch.randn(base.shape, generator=g)).cuda()
+        # a perturbation shaped like the estimate keeps the curvature term small
+        V = V * base.abs() / base.abs().max()
+        h = 1e-3 * float(base.abs().max())
+        if which == "O":
+            fp = eng.amp_loss(pr["to"] + h * V, pr["tp"], pr["idx"])
+            fm = eng.amp_loss(pr["to"] - h * V, pr["tp"], pr["idx"])
+            ana = float(torch.real(torch.vdot(go.flatten(), V.flatten())))
+        else:
+            fp = eng.amp_loss(pr["to"], pr["tp"] + h * V, pr["idx"])
+            fm = eng.amp_loss(pr["to"], pr["tp"] - h * V, pr["idx"])
+            ana = float(torch.real(torch.vdot(gp.flatten(), V.flatten())))
+        fd = (fp - fm) / (2 * h)
+        print(which, fd, ana)
+        assert abs(fd - ana) <= 2e-2 * abs(ana), (which, fd, ana)
+
+
+def test_adam_descends(torch_cuda):
+    """Gradient reconstruction with Adam on minibatches lowers the loss."""
+    torch = torch_cuda
+    from paper_2308_10674_amd import Engine, amplitude_loss
+    wl = sim.make_config(1, n_positions=300)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(wl.positions, wl.intensities)
+    O = torch.from_numpy(wl.object0.astype(np.complex64)).cuda().requires_grad_(True)
+    P = torch.from_numpy(wl.probe0.astype(np.complex64)).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([O, P], lr=1e-2)
+    rng = np.random.default_rng(3)
+    full = np.arange(wl.count)
+    first = eng.amp_loss(O, P, full)
+    for epoch in range(4):
+        perm = rng.permutation(wl.count)
+        for b in range(0, wl.count, 100):
+            opt.zero_grad()
+            amplitude_loss(eng, O, P, perm[b:b + 100]).backward()
+            opt.step()
+    last = eng.amp_loss(O, P, full)
+    print("adam loss", first, "->", last)
+    assert last < 0.8 * first
+
+
+def test_bad_arguments(problem, torch_cuda):
+    torch = torch_cuda
+    from paper_2308_10674_amd import PtycError
+    pr = problem
+    with pytest.raises(PtycError):
+        pr["eng"].amp_loss(pr["to"], pr["tp"], [10 ** 6])
+    assert pr["eng"].amp_loss(pr["to"], pr["tp"], []) == 0.0

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import sim
-from _parity import (RTOL, check_batches, check_rows, engine_for, library_schedule, oracle_sweep,
+from _parity import (RTOL, check_batches, check_rows, engine_for, library_schedule, oracle_sweep, progress,
                      run_batches_resynced, run_resynced, strict_schedule)
 
 pytestmark = pytest.mark.gpu
@@ -121,13 +121,15 @@ def test_live_growth_every_batch():
         eng.sweep(1, order=order, batch_offsets=off)
 
 
-@pytest.mark.parametrize("cfg,n_batches", [(1, 121), (2, 70)])
+@pytest.mark.parametrize("cfg,n_batches", [(1, 121), (2, 31)])
 def test_full_size_sampled_batches(cfg, n_batches):
     """The full 128 px (3600 positions, 1024^2) and 256 px (20000 positions,
     2048^2) workloads, as the benchmark runs them: the oracle follows the
     library's first sweep for ``n_batches`` batches and every 10th batch is
     re-synced and compared."""
+    progress(f"full-size workload {cfg}: generating")
     wl = sim.make_config(cfg)
+    progress(f"full-size workload {cfg}: {wl.count} positions generated")
     from paper_2308_10674_amd import Engine
     import torch
     eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
