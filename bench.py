@@ -33,14 +33,43 @@ def algorithmic_bytes(n: int) -> int:
     return 20 * n * n
 
 
-def load_traffic(path):
-    """HBM bytes per position update measured with rocprofv3 counters, if a
-    summary with that figure is committed (profiles/*.json)."""
+# algorithmic bytes per position update of each kernel: what it must move of
+# the method's own state (the exchange buffers are not counted)
+KERNEL_BYTES = {
+    "k_rows_fwd": lambda n: 8 * n * n,    # read the object window
+    "k_cols": lambda n: 4 * n * n,        # read sqrt(I)
+    "k_rows_inv": lambda n: 16 * n * n,   # read and write the object window
+    "k_sweep": lambda n: 20 * n * n,      # the whole update
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2308_10674_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel, n):
+    """HBM bytes per launch of ``kernel`` at pattern size ``n`` from the
+    committed rocprofv3 counter summaries (lines 'traffic-json: {...}' in
+    profiles/*.md), if they were taken on the current kernel source."""
+    pdir = os.path.join(ROOT, "profiles")
+    h = kernel_source_hash()
     try:
-        with open(path) as f:
-            return json.load(f)
-    except Exception:
+        names = sorted(os.listdir(pdir))
+    except OSError:
         return None
+    for name in names:
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if line.startswith("traffic-json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("kernel") == kernel and rec.get("n") == n and rec.get("kernels_sha256") == h:
+                        return rec
+    return None
 
 
 def run_gpu(cfg_id, steps, warmup, form, positions=None):
@@ -76,9 +105,33 @@ def run_gpu(cfg_id, steps, warmup, form, positions=None):
     updates = wl.count * steps
     rate = updates / (ms / 1e3)
     achieved = algorithmic_bytes(wl.n) * rate / 1e9
+    # per-kernel event timing over the same number of sweeps (a second pass,
+    # so the events do not disturb the timed region above)
+    eng.profile(True)
+    eng.sweep(steps)
+    kern = eng.profile_read()
+    eng.profile(False)
     return dict(wl=wl, ms=ms, rate=rate, achieved_gbs=achieved, batches=int(len(sizes)),
                 mean_batch=float(sizes.mean()), max_batch=int(sizes.max()), gen_s=gen_s,
-                ingest_s=ingest_s, err=float(err))
+                ingest_s=ingest_s, err=float(err), kernels=kern)
+
+
+def roofline_of(r):
+    """Roofline entry of the dominant kernel (largest summed event time)."""
+    n = r["wl"].n
+    name, (ms, launches, units) = max(r["kernels"].items(), key=lambda kv: kv[1][0])
+    per_launch_bytes = KERNEL_BYTES[name](n) * units / launches
+    avg_s = ms / 1e3 / launches
+    achieved = per_launch_bytes / avg_s / 1e9
+    tr = load_traffic(name, n)
+    return {
+        "bound": "hbm", "kernel": f"{name}<{n}>", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": None if tr is None else int(tr["bytes_per_launch"]),
+        "algorithmic_bytes_per_launch": round(per_launch_bytes),
+        "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
+        "kernel_times_ms": {k: round(v[0], 3) for k, v in r["kernels"].items()},
+    }
 
 
 def cpu_baseline(cfg_id, budget_s):
@@ -158,12 +211,11 @@ def main():
             "batches_per_sweep": r["batches"], "mean_batch": round(r["mean_batch"], 2),
             "max_batch": r["max_batch"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_sweep<128> (one launch per sweep)" if args.form == "persistent" else "all launches of a sweep",
-            "achieved": round(r["achieved_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 5), "traffic": None,
+        "roofline": roofline_of(r),
+        "path": {
+            "achieved": round(r["achieved_gbs"], 2), "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 5),
             "bytes_per_update": algorithmic_bytes(wl.n),
+            "note": "whole sweep: 20 N^2 algorithmic bytes per position update over the timed wall time",
         },
         "error_after": r["err"],
     }
@@ -175,6 +227,7 @@ def main():
             "workload": "ePIE 256x256 patterns, 20000-position Fermat spiral, 2048x2048 object",
             "achieved": round(r2["achieved_gbs"], 2), "frac": round(r2["achieved_gbs"] / HBM_PEAK_GBS, 5),
             "batches_per_sweep": r2["batches"], "mean_batch": round(r2["mean_batch"], 2),
+            "roofline": roofline_of(r2),
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds)

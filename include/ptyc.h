@@ -161,6 +161,22 @@ int ptyc_set_form(ptyc_ctx* ctx, int form);
 /* The current launch form (-1 for a NULL context). */
 int ptyc_get_form(const ptyc_ctx* ctx);
 
+/* Per-kernel timing.  While enabled, every sweep records HIP events on the
+ * context's stream around each kernel launch (this adds a little host
+ * work per launch); ptyc_profile_read synchronises the stream and returns,
+ * for one kernel kind, the summed event time in milliseconds, the number of
+ * launches and the number of position updates those launches processed.
+ * ptyc_profile(ctx, enable) resets the totals.  Errors: PTYC_ERR_ARG for an
+ * unknown kind or NULL outputs. */
+#define PTYC_KERNEL_ROWS_FWD 0    /* exit wave and row FFTs */
+#define PTYC_KERNEL_COLS 1        /* column FFTs, modulus replacement, inverse column FFTs */
+#define PTYC_KERNEL_ROWS_INV 2    /* inverse row FFTs, object step, batch probe step */
+#define PTYC_KERNEL_SWEEP 3       /* the persistent sweep kernel */
+#define PTYC_KERNEL_KINDS 4
+int ptyc_profile(ptyc_ctx* ctx, int enable);
+int ptyc_profile_read(ptyc_ctx* ctx, int kind, double* total_ms, int64_t* launches,
+                      int64_t* positions);
+
 /* Number of loaded positions (-1 for a NULL context). */
 int64_t ptyc_num_positions(const ptyc_ctx* ctx);
 /* Number of completed sweeps (drives the default shuffle). */

@@ -20,6 +20,11 @@ PTYC_MODE_COLOURED = 1
 PTYC_FORM_DEFAULT = 0
 PTYC_FORM_BATCH = 1
 PTYC_FORM_PERSISTENT = 2
+PTYC_KERNEL_ROWS_FWD = 0
+PTYC_KERNEL_COLS = 1
+PTYC_KERNEL_ROWS_INV = 2
+PTYC_KERNEL_SWEEP = 3
+KERNEL_NAMES = {0: "k_rows_fwd", 1: "k_cols", 2: "k_rows_inv", 3: "k_sweep"}
 PTYC_I_IS_SQRT = 1
 PTYC_I_CENTERED = 2
 
@@ -54,6 +59,8 @@ SIGNATURES = {
     "ptyc_set_probe": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_amp_loss": (C.c_int, [_P, _P, _P, _I64P, C.c_int64, C.c_float, _P, _P, _DP]),
     "ptyc_set_form": (C.c_int, [_P, C.c_int]),
+    "ptyc_profile": (C.c_int, [_P, C.c_int]),
+    "ptyc_profile_read": (C.c_int, [_P, C.c_int, _DP, _I64P, _I64P]),
     "ptyc_get_form": (C.c_int, [_P]),
     "ptyc_num_positions": (C.c_int64, [_P]),
     "ptyc_sweep_count": (C.c_int64, [_P]),

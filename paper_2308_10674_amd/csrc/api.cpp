@@ -60,6 +60,16 @@ struct ptyc_ctx {
     bool upload_pending = false;
 
     size_t dev_bytes = 0, dev_limit = 0;
+
+    // optional per-kernel timing with events on the context's stream
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;      // created on demand, reused
+    size_t ev_used = 0;
+    struct Mark { int kind; size_t e0, e1; int64_t units; };
+    std::vector<Mark> marks;               // pending intervals
+    double prof_ms[PTYC_KERNEL_KINDS] = {};
+    int64_t prof_launches[PTYC_KERNEL_KINDS] = {};
+    int64_t prof_units[PTYC_KERNEL_KINDS] = {};
 };
 
 namespace {
@@ -211,6 +221,34 @@ int refresh_probe_max(ptyc_ctx* c) {
     return PTYC_OK;
 }
 
+// next n events of the profiling pool (created as needed)
+int take_events(ptyc_ctx* c, size_t n, size_t* first) {
+    while (c->ev_pool.size() < c->ev_used + n) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    *first = c->ev_used;
+    c->ev_used += n;
+    return PTYC_OK;
+}
+
+// fold the pending intervals into the totals (synchronises the stream)
+int collect_profile(ptyc_ctx* c) {
+    if (c->marks.empty()) return PTYC_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (const auto& m : c->marks) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[m.e0], c->ev_pool[m.e1]));
+        c->prof_ms[m.kind] += ms;
+        c->prof_launches[m.kind] += 1;
+        c->prof_units[m.kind] += m.units;
+    }
+    c->marks.clear();
+    c->ev_used = 0;
+    return PTYC_OK;
+}
+
 // after a synchronisation: did a persistent sweep give up on a barrier?
 int check_fault(ptyc_ctx* c) {
     if (!c->sync.p) return PTYC_OK;
@@ -305,6 +343,7 @@ void ptyc_destroy(ptyc_ctx* c) {
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c->colouring;
     delete c;
 }
@@ -334,6 +373,31 @@ int ptyc_set_form(ptyc_ctx* c, int form) {
 }
 
 int ptyc_get_form(const ptyc_ctx* c) { return c ? c->form : -1; }
+
+int ptyc_profile(ptyc_ctx* c, int enable) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if ((rc = collect_profile(c)) != PTYC_OK) return rc;
+    c->prof = enable != 0;
+    for (int k = 0; k < PTYC_KERNEL_KINDS; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_launches[k] = 0;
+        c->prof_units[k] = 0;
+    }
+    return PTYC_OK;
+}
+
+int ptyc_profile_read(ptyc_ctx* c, int kind, double* total_ms, int64_t* launches, int64_t* positions) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (kind < 0 || kind >= PTYC_KERNEL_KINDS || !total_ms || !launches || !positions)
+        return fail(c, PTYC_ERR_ARG, "bad kernel kind or NULL output");
+    if ((rc = collect_profile(c)) != PTYC_OK) return rc;
+    *total_ms = c->prof_ms[kind];
+    *launches = c->prof_launches[kind];
+    *positions = c->prof_units[kind];
+    return PTYC_OK;
+}
 
 int ptyc_add_positions(ptyc_ctx* c, int64_t count, const int32_t* pos_yx, const float* inten,
                        int mem_kind) {
@@ -517,14 +581,33 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
             ctl.bar = (unsigned*)c->sync.p;
             ctl.fault = (int*)((unsigned*)c->sync.p + 1);
             ctl.nblocks = (unsigned)c->capacity;
+            size_t e0 = 0;
+            if (c->prof) {
+                if ((rc = take_events(c, 2, &e0)) != PTYC_OK) return rc;
+                HIPCHK(c, hipEventRecord(c->ev_pool[e0], c->stream));
+            }
             HIPCHK(c, launch_sweep(c->cfg.n, a, ctl, (int)max_b, c->stream));
+            if (c->prof) {
+                HIPCHK(c, hipEventRecord(c->ev_pool[e0 + 1], c->stream));
+                c->marks.push_back({PTYC_KERNEL_SWEEP, e0, e0 + 1, olen});
+            }
         } else {
             const auto& f = offs[(size_t)s];
             for (size_t b = 0; b + 1 < f.size(); ++b) {
                 a.off = f[b];
                 a.bsize = (int)(f[b + 1] - f[b]);
                 if (a.bsize == 0) continue;
-                HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
+                if (c->prof) {
+                    size_t e0 = 0;
+                    if ((rc = take_events(c, 4, &e0)) != PTYC_OK) return rc;
+                    hipEvent_t ev[4] = {c->ev_pool[e0], c->ev_pool[e0 + 1], c->ev_pool[e0 + 2], c->ev_pool[e0 + 3]};
+                    HIPCHK(c, launch_batch(c->cfg.n, a, c->stream, ev));
+                    c->marks.push_back({PTYC_KERNEL_ROWS_FWD, e0, e0 + 1, a.bsize});
+                    c->marks.push_back({PTYC_KERNEL_COLS, e0 + 1, e0 + 2, a.bsize});
+                    c->marks.push_back({PTYC_KERNEL_ROWS_INV, e0 + 2, e0 + 3, a.bsize});
+                } else {
+                    HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
+                }
             }
         }
         if (err_out)

@@ -57,7 +57,9 @@ struct SweepCtl {
 bool supported_n(int n);
 Shape shape_for(int n, int form);
 
-hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s);
+// ev: NULL, or four events recorded before the first kernel and after each
+// of the three kernels of the batch
+hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 // the partial maxima of |P|^2 of the current probe (no update)
 hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel

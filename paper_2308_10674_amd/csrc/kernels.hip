@@ -523,14 +523,18 @@ Shape shape_n(int form) {
 }
 
 template <int N>
-hipError_t batch_n(const BatchArgs& a, hipStream_t s) {
+hipError_t batch_n(const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
     using rg = RowG<N, Tile<N>::RB>;
     using cg = ColG<N, Tile<N>::CB>;
+    if (ev) (void)hipEventRecord(ev[0], s);
     if (a.bsize > 0) {
         hipLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
+        if (ev) (void)hipEventRecord(ev[1], s);
         hipLaunchKernelGGL(k_cols<N>, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
+        if (ev) (void)hipEventRecord(ev[2], s);
     }
     hipLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
 
@@ -616,8 +620,8 @@ Shape shape_for(int n, int form) {
     return Shape{0, 0, 0};
 }
 
-hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s) {
-    PTYC_DISPATCH(n, batch_n<N>(a, s));
+hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
+    PTYC_DISPATCH(n, batch_n<N>(a, s, ev));
     return hipErrorInvalidValue;
 }
 

@@ -180,6 +180,23 @@ class Engine:
                                      C.byref(loss)), self._ctx)
         return (loss.value, go, gp) if grad else loss.value
 
+    # ------------------------------------------------------------ profiling
+    def profile(self, enable=True):
+        """Start (reset) or stop per-kernel event timing."""
+        _check(L.lib().ptyc_profile(self._ctx, 1 if enable else 0), self._ctx)
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches, position updates)}."""
+        out = {}
+        for k, name in L.KERNEL_NAMES.items():
+            ms = C.c_double()
+            n = C.c_int64()
+            u = C.c_int64()
+            _check(L.lib().ptyc_profile_read(self._ctx, k, C.byref(ms), C.byref(n), C.byref(u)), self._ctx)
+            if n.value:
+                out[name] = (ms.value, n.value, u.value)
+        return out
+
     @property
     def form(self) -> str:
         f = int(L.lib().ptyc_get_form(self._ctx))
