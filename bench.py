@@ -134,6 +134,51 @@ def roofline_of(r):
     }
 
 
+def run_multi(steps, warmup, n_scans=16):
+    """Sixteen independent scans of uneven size (pattern sizes 64/128/256,
+    500-5000 positions, raster or spiral): per-scan sweeps one after the
+    other against all scans advanced together by ptyc_sweep_multi."""
+    import torch
+
+    import sim
+    from paper_2308_10674_amd import Engine, sweep_multi
+
+    t0 = time.time()
+    scans = sim.make_multiscan(n_scans)
+    gen_s = time.time() - t0
+    engs = []
+    for wl in scans:
+        e = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+        e.add_positions(torch.from_numpy(wl.positions).cuda(), torch.from_numpy(wl.intensities).cuda())
+        engs.append(e)
+        wl.intensities = None
+    total = sum(wl.count for wl in scans)
+    sweep_multi(engs, warmup)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for e in engs:
+        e.sweep(steps)
+    ev[1].record()
+    ev[2].record()
+    sweep_multi(engs, steps)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ms_seq = ev[0].elapsed_time(ev[1])
+    ms_multi = ev[2].elapsed_time(ev[3])
+    bytes_per_sweep = sum(20 * wl.n * wl.n * wl.count for wl in scans)
+    return {
+        "workload": f"{n_scans} independent scans, pattern sizes {sorted(set(int(wl.n) for wl in scans))}, "
+                    f"{total} positions in total ({min(wl.count for wl in scans)}-{max(wl.count for wl in scans)} per scan)",
+        "steps": steps, "generation_s": round(gen_s, 1),
+        "sequential": {"value": round(total * steps / (ms_seq / 1e3), 1), "ms_per_step": round(ms_seq / steps, 3)},
+        "together": {"value": round(total * steps / (ms_multi / 1e3), 1), "ms_per_step": round(ms_multi / steps, 3),
+                     "achieved": round(bytes_per_sweep * steps / (ms_multi / 1e3) / 1e9, 2),
+                     "frac": round(bytes_per_sweep * steps / (ms_multi / 1e3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "unit": "position updates/s",
+    }
+
+
 def cpu_baseline(cfg_id, budget_s):
     """The FP64 oracle on the host: coloured sweep over the same workload's
     first batches until ``budget_s`` seconds of work are done."""
@@ -169,6 +214,8 @@ def main():
                     help="batch: three launches per batch; persistent: one cooperative kernel per sweep")
     ap.add_argument("--no-256", action="store_true", help="skip the 256 px workload")
     ap.add_argument("--steps-256", type=int, default=3)
+    ap.add_argument("--multi", action="store_true", help="also time 16 independent scans advanced together")
+    ap.add_argument("--steps-multi", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -229,6 +276,8 @@ def main():
             "batches_per_sweep": r2["batches"], "mean_batch": round(r2["mean_batch"], 2),
             "roofline": roofline_of(r2),
         }
+    if args.multi:
+        out["multi16"] = run_multi(args.steps_multi, 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -134,6 +134,20 @@ int ptyc_sweep(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
                int64_t order_len, const int64_t* batch_offsets,
                int64_t n_batches, double* err_out);
 
+/* Run n_sweeps sweeps on each of n_ctx independent contexts together
+ * (several scans of uneven size and pattern size at once).  Every context
+ * follows its own default schedule, exactly as ptyc_sweep(ctx, n_sweeps,
+ * NULL, ...) would, and produces the same bytes; a step advances every
+ * unfinished context by one batch and, per pattern size, launches each
+ * stage once for all of them, so small batches share the GPU.  All contexts
+ * must use the same device and stream; n_ctx <= PTYC_MULTI_MAX.  err_out:
+ * NULL or n_ctx * n_sweeps doubles (context-major) receiving each sweep's
+ * running Fourier error (this synchronises).  The call synchronises the
+ * stream once before it enqueues work.  Errors: PTYC_ERR_ARG (NULL or
+ * repeated context, mixed streams, too many contexts). */
+#define PTYC_MULTI_MAX 64
+int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, double* err_out);
+
 /* Export the schedule the next sweep with order == NULL would run:
  * order receives n_loaded indices, batch_offsets n_batches+1 offsets (host
  * arrays with room for n_loaded and n_loaded+1 entries; either may be NULL

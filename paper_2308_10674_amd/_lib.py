@@ -52,6 +52,7 @@ SIGNATURES = {
     "ptyc_init": (C.c_int, [C.POINTER(_P), C.POINTER(Config), _P, _P, C.c_int, _P]),
     "ptyc_add_positions": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int]),
     "ptyc_sweep": (C.c_int, [_P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64, _DP]),
+    "ptyc_sweep_multi": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP]),
     "ptyc_get_schedule": (C.c_int, [_P, _I64P, _I64P, _I64P]),
     "ptyc_get_object": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_get_probe": (C.c_int, [_P, _P, C.c_int]),

@@ -48,6 +48,7 @@ struct ptyc_ctx {
     DevBuf err_part, err_dev;
     DevBuf bad;                      // int flag for ingest validation
     DevBuf sync;                     // [0] barrier counter, [1] barrier fault flag
+    DevBuf multi;                    // batch descriptors of a multi-context call
     DevBuf staging;                  // host intensities staged on the device
 
     // host state
@@ -339,7 +340,7 @@ void ptyc_destroy(ptyc_ctx* c) {
     if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
                       &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
-                      &c->err_dev, &c->bad, &c->sync, &c->staging};
+                      &c->err_dev, &c->bad, &c->sync, &c->multi, &c->staging};
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -478,12 +479,20 @@ int ptyc_get_schedule(ptyc_ctx* c, int64_t* order, int64_t* off, int64_t* n_batc
     return PTYC_OK;
 }
 
-int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t order_len,
-               const int64_t* off, int64_t n_batches, double* err_out) {
-    int rc = usable(c);
-    if (rc) return rc;
-    if (n_sweeps < 0) return fail(c, PTYC_ERR_ARG, "n_sweeps must be >= 0");
-    if (n_sweeps == 0) return PTYC_OK;
+}  // extern "C"
+
+namespace {
+
+// Schedules of the sweeps of one call, before anything reaches the device.
+struct Plan {
+    std::vector<std::vector<int64_t>> orders, offs;
+    int64_t olen = 0, nb = 0, max_b = 1;
+};
+
+// Validate the arguments of a sweep call and build its schedules.  Leaves
+// p.olen == 0 when there is nothing to run.
+int plan_sweeps(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t order_len, const int64_t* off,
+                int64_t n_batches, Plan& p) {
     std::string why;
     const bool strict = c->cfg.mode == PTYC_MODE_STRICT;
     if (order) {
@@ -500,54 +509,53 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                     return fail(c, PTYC_ERR_ARG, "order index " + std::to_string(order[i]) + " is not a loaded position");
         }
     }
-    if (c->n_loaded == 0 || (order && order_len == 0)) {
-        if (err_out)
-            for (int s = 0; s < n_sweeps; ++s) err_out[s] = 0.0;
-        c->sweeps_done += n_sweeps;
-        return PTYC_OK;
-    }
-
-    // host schedules of all sweeps
-    std::vector<std::vector<int64_t>> orders((size_t)n_sweeps), offs((size_t)n_sweeps);
+    p = Plan{};
+    if (c->n_loaded == 0 || (order && order_len == 0)) return PTYC_OK;
+    p.orders.resize((size_t)n_sweeps);
+    p.offs.resize((size_t)n_sweeps);
     for (int s = 0; s < n_sweeps; ++s) {
         if (order) {
-            orders[(size_t)s].assign(order, order + order_len);
+            p.orders[(size_t)s].assign(order, order + order_len);
             if (strict) {
-                offs[(size_t)s].resize((size_t)order_len + 1);
-                for (int64_t i = 0; i <= order_len; ++i) offs[(size_t)s][(size_t)i] = i;
+                p.offs[(size_t)s].resize((size_t)order_len + 1);
+                for (int64_t i = 0; i <= order_len; ++i) p.offs[(size_t)s][(size_t)i] = i;
             } else {
-                offs[(size_t)s].assign(off, off + n_batches + 1);
+                p.offs[(size_t)s].assign(off, off + n_batches + 1);
             }
         } else {
-            default_schedule(c, c->sweeps_done + s, orders[(size_t)s], offs[(size_t)s]);
+            default_schedule(c, c->sweeps_done + s, p.orders[(size_t)s], p.offs[(size_t)s]);
         }
     }
-    const int64_t olen = (int64_t)orders[0].size();
-    const int64_t nb = (int64_t)offs[0].size() - 1;
+    p.olen = (int64_t)p.orders[0].size();
+    p.nb = (int64_t)p.offs[0].size() - 1;
     for (int s = 1; s < n_sweeps; ++s)
-        if ((int64_t)offs[(size_t)s].size() - 1 != nb) return fail(c, PTYC_ERR_ARG, "internal: batch count varies");
-    int64_t max_b = 1;
+        if ((int64_t)p.offs[(size_t)s].size() - 1 != p.nb) return fail(c, PTYC_ERR_ARG, "internal: batch count varies");
     for (int s = 0; s < n_sweeps; ++s)
-        for (size_t b = 0; b + 1 < offs[(size_t)s].size(); ++b)
-            max_b = std::max(max_b, offs[(size_t)s][b + 1] - offs[(size_t)s][b]);
+        for (size_t b = 0; b + 1 < p.offs[(size_t)s].size(); ++b)
+            p.max_b = std::max(p.max_b, p.offs[(size_t)s][b + 1] - p.offs[(size_t)s][b]);
+    return PTYC_OK;
+}
 
-    // buffers
+// Size the work buffers for a plan, upload its orders and offsets, refresh
+// the probe maxima in the layout of `form`.
+int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
+    int rc;
     const size_t nn = (size_t)c->cfg.n * c->cfg.n;
-    if (max_b > c->slots) {
-        if ((rc = ensure(c, c->scratch, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
-        if ((rc = ensure(c, c->dprobe, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
-        if ((rc = ensure(c, c->winmax, (size_t)max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
-        c->slots = max_b;
+    if (p.max_b > c->slots) {
+        if ((rc = ensure(c, c->scratch, (size_t)p.max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->dprobe, (size_t)p.max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->winmax, (size_t)p.max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
+        c->slots = p.max_b;
     }
-    const size_t obytes = (size_t)n_sweeps * olen * sizeof(int64_t);
-    const size_t fbytes = (size_t)n_sweeps * (nb + 1) * sizeof(int64_t);
+    const size_t obytes = (size_t)n_sweeps * p.olen * sizeof(int64_t);
+    const size_t fbytes = (size_t)n_sweeps * (p.nb + 1) * sizeof(int64_t);
     if (c->upload_pending) {
         HIPCHK(c, hipEventSynchronize(c->upload_done));
         c->upload_pending = false;
     }
     if ((rc = ensure(c, c->order, obytes)) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->offs, fbytes)) != PTYC_OK) return rc;
-    if ((rc = ensure(c, c->err_part, (size_t)olen * max_col_blocks(c) * sizeof(double))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_part, (size_t)p.olen * max_col_blocks(c) * sizeof(double))) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->err_dev, (size_t)n_sweeps * sizeof(double))) != PTYC_OK) return rc;
     if (c->pinned_bytes < obytes + fbytes) {
         if (c->pinned_order) (void)hipHostFree(c->pinned_order);
@@ -560,17 +568,51 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
         }
         c->pinned_bytes = obytes + fbytes;
     }
-    int64_t* pin_off = c->pinned_order + (size_t)n_sweeps * olen;
+    int64_t* pin_off = c->pinned_order + (size_t)n_sweeps * p.olen;
     for (int s = 0; s < n_sweeps; ++s) {
-        std::memcpy(c->pinned_order + (size_t)s * olen, orders[(size_t)s].data(), (size_t)olen * sizeof(int64_t));
-        std::memcpy(pin_off + (size_t)s * (nb + 1), offs[(size_t)s].data(), (size_t)(nb + 1) * sizeof(int64_t));
+        std::memcpy(c->pinned_order + (size_t)s * p.olen, p.orders[(size_t)s].data(), (size_t)p.olen * sizeof(int64_t));
+        std::memcpy(pin_off + (size_t)s * (p.nb + 1), p.offs[(size_t)s].data(), (size_t)(p.nb + 1) * sizeof(int64_t));
     }
     HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, obytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->offs.p, pin_off, fbytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
     c->upload_pending = true;
+    BatchArgs a = base_args(c);
+    a.bsize = 0;
+    HIPCHK(c, launch_probe_reduce(c->cfg.n, a, form, c->stream));
+    return PTYC_OK;
+}
 
-    if ((rc = refresh_probe_max(c)) != PTYC_OK) return rc;
+// the error-metric reduction of sweep s of a plan (batch-form layout when
+// batch_layout, else the context's form)
+int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, bool batch_layout) {
+    const int gc = batch_layout ? c->sb.col_blocks : shape_of(c).col_blocks;
+    const int64_t* ord = (const int64_t*)c->order.p + (size_t)s * p.olen;
+    HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, p.olen * gc, ord, p.olen, (const double*)c->sum_i.p,
+                                (double*)c->err_dev.p + s, c->stream));
+    return PTYC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t order_len,
+               const int64_t* off, int64_t n_batches, double* err_out) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (n_sweeps < 0) return fail(c, PTYC_ERR_ARG, "n_sweeps must be >= 0");
+    if (n_sweeps == 0) return PTYC_OK;
+    Plan p;
+    if ((rc = plan_sweeps(c, n_sweeps, order, order_len, off, n_batches, p)) != PTYC_OK) return rc;
+    if (p.olen == 0) {
+        if (err_out)
+            for (int s = 0; s < n_sweeps; ++s) err_out[s] = 0.0;
+        c->sweeps_done += n_sweeps;
+        return PTYC_OK;
+    }
+    if ((rc = stage_plan(c, p, n_sweeps, c->form)) != PTYC_OK) return rc;
+    const int64_t olen = p.olen, nb = p.nb;
     for (int s = 0; s < n_sweeps; ++s) {
         BatchArgs a = base_args(c);
         a.order = (const int64_t*)c->order.p + (size_t)s * olen;
@@ -586,13 +628,13 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                 if ((rc = take_events(c, 2, &e0)) != PTYC_OK) return rc;
                 HIPCHK(c, hipEventRecord(c->ev_pool[e0], c->stream));
             }
-            HIPCHK(c, launch_sweep(c->cfg.n, a, ctl, (int)max_b, c->stream));
+            HIPCHK(c, launch_sweep(c->cfg.n, a, ctl, (int)p.max_b, c->stream));
             if (c->prof) {
                 HIPCHK(c, hipEventRecord(c->ev_pool[e0 + 1], c->stream));
                 c->marks.push_back({PTYC_KERNEL_SWEEP, e0, e0 + 1, olen});
             }
         } else {
-            const auto& f = offs[(size_t)s];
+            const auto& f = p.offs[(size_t)s];
             for (size_t b = 0; b + 1 < f.size(); ++b) {
                 a.off = f[b];
                 a.bsize = (int)(f[b + 1] - f[b]);
@@ -610,9 +652,7 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                 }
             }
         }
-        if (err_out)
-            HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, olen * shape_of(c).col_blocks, a.order, olen,
-                                        (const double*)c->sum_i.p, (double*)c->err_dev.p + s, c->stream));
+        if (err_out && (rc = launch_sweep_error(c, p, s, false)) != PTYC_OK) return rc;
     }
     c->sweeps_done += n_sweeps;
     if (err_out) {
@@ -620,6 +660,93 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return check_fault(c);
+    }
+    return PTYC_OK;
+}
+
+int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, double* err_out) {
+    if (!ctxs || n_ctx <= 0 || n_ctx > PTYC_MULTI_MAX || n_sweeps < 0) return PTYC_ERR_ARG;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return PTYC_ERR_ARG;
+        int rc = usable(ctxs[i]);
+        if (rc) return rc;
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) return fail(ctxs[i], PTYC_ERR_ARG, "a context appears twice");
+        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device)
+            return fail(ctxs[i], PTYC_ERR_ARG, "all contexts must share one device and stream");
+    }
+    if (n_sweeps == 0) return PTYC_OK;
+    int rc;
+    std::vector<Plan> plans((size_t)n_ctx);
+    for (int i = 0; i < n_ctx; ++i)
+        if ((rc = plan_sweeps(ctxs[i], n_sweeps, nullptr, 0, nullptr, 0, plans[(size_t)i])) != PTYC_OK) return rc;
+    for (int i = 0; i < n_ctx; ++i)
+        if (plans[(size_t)i].olen > 0 && (rc = stage_plan(ctxs[i], plans[(size_t)i], n_sweeps, kFormBatch)) != PTYC_OK)
+            return rc;
+    // one step advances every unfinished context by one batch; per pattern
+    // size, each step is three launches covering all of that size's batches
+    int64_t steps = 0;
+    for (int i = 0; i < n_ctx; ++i) steps = std::max(steps, (int64_t)n_sweeps * plans[(size_t)i].nb);
+    const int sizes[] = {16, 32, 64, 128, 256};
+    std::vector<BatchArgs> tab;
+    struct Launch { int n; size_t first; int count; };
+    std::vector<Launch> launches;                 // per (step, size) with any work
+    std::vector<std::vector<std::pair<int, int>>> ends((size_t)steps);  // (context, sweep) finishing at a step
+    std::vector<size_t> step_first((size_t)steps + 1, 0);               // launches of step k: [first[k], first[k+1])
+    for (int64_t k = 0; k < steps; ++k) {
+        step_first[(size_t)k] = launches.size();
+        for (int n : sizes) {
+            Launch L{n, tab.size(), 0};
+            for (int i = 0; i < n_ctx; ++i) {
+                ptyc_ctx* c = ctxs[i];
+                const Plan& p = plans[(size_t)i];
+                if (c->cfg.n != n || p.olen == 0 || k >= (int64_t)n_sweeps * p.nb) continue;
+                const int s = (int)(k / p.nb);
+                const int64_t b = k % p.nb;
+                BatchArgs a = base_args(c);
+                a.row_blocks = c->sb.row_blocks;
+                a.npmax = c->sb.probe_blocks;
+                a.order = (const int64_t*)c->order.p + (size_t)s * p.olen;
+                a.off = p.offs[(size_t)s][(size_t)b];
+                a.bsize = (int)(p.offs[(size_t)s][(size_t)b + 1] - a.off);
+                tab.push_back(a);
+                ++L.count;
+                if (b == p.nb - 1) ends[(size_t)k].push_back({i, s});
+            }
+            if (L.count) launches.push_back(L);
+        }
+    }
+    step_first[(size_t)steps] = launches.size();
+    ptyc_ctx* c0 = ctxs[0];
+    // the descriptor table may still be read by an earlier call's kernels
+    HIPCHK(c0, hipStreamSynchronize(c0->stream));
+    if ((rc = ensure(c0, c0->multi, tab.size() * sizeof(BatchArgs))) != PTYC_OK) return rc;
+    if (!tab.empty()) {
+        HIPCHK(c0, hipMemcpyAsync(c0->multi.p, tab.data(), tab.size() * sizeof(BatchArgs), hipMemcpyHostToDevice,
+                                  c0->stream));
+        HIPCHK(c0, hipStreamSynchronize(c0->stream));
+    }
+    for (int64_t k = 0; k < steps; ++k) {
+        for (size_t li = step_first[(size_t)k]; li < step_first[(size_t)k + 1]; ++li) {
+            const Launch& L = launches[li];
+            HIPCHK(c0, launch_batch_multi(L.n, (const BatchArgs*)c0->multi.p + L.first, tab.data() + L.first, L.count,
+                                          c0->stream));
+        }
+        if (err_out)
+            for (auto [i, s] : ends[(size_t)k])
+                if ((rc = launch_sweep_error(ctxs[i], plans[(size_t)i], s, true)) != PTYC_OK) return rc;
+    }
+    for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps_done += n_sweeps;
+    if (err_out) {
+        for (int i = 0; i < n_ctx; ++i) {
+            if (plans[(size_t)i].olen == 0) {
+                for (int s = 0; s < n_sweeps; ++s) err_out[(size_t)i * n_sweeps + s] = 0.0;
+                continue;
+            }
+            HIPCHK(c0, hipMemcpyAsync(err_out + (size_t)i * n_sweeps, ctxs[i]->err_dev.p,
+                                      (size_t)n_sweeps * sizeof(double), hipMemcpyDeviceToHost, c0->stream));
+        }
+        HIPCHK(c0, hipStreamSynchronize(c0->stream));
     }
     return PTYC_OK;
 }

@@ -62,6 +62,12 @@ Shape shape_for(int n, int form);
 hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 // the partial maxima of |P|^2 of the current probe (no update)
 hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s);
+// one batch of each of `count` independent reconstructions with pattern
+// size n (three launches): dev_tab on the device, host_tab the same
+// descriptors on the host (for the grid layout); count <= kMultiMax
+constexpr int kMultiMax = 64;
+hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* host_tab, int count,
+                              hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel
 hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s);
 // amplitude loss over one batch of disjoint windows; grad: also accumulate

@@ -379,6 +379,56 @@ __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     stage_rows_inv<N, g::R, g::S>(a, blockIdx.x, lds, dl, red);
 }
 
+// Several reconstructions at once: workgroup b belongs to descriptor i with
+// start[i] <= b < start[i+1]; the descriptor is uniform, so it lives in
+// scalar registers.
+struct MultiArgs {
+    const BatchArgs* tab;
+    int count;
+    int start[kMultiMax + 1];
+};
+
+__device__ inline int multi_find(const MultiArgs& m) {
+    int i = 0;
+    while (i + 1 < m.count && (int)blockIdx.x >= m.start[i + 1]) ++i;
+    return i;
+}
+
+template <int N>
+__global__ __launch_bounds__(kRowNT<N>) void k_rows_fwd_multi(MultiArgs m) {
+    constexpr int RB = Tile<N>::RB;
+    using g = RowG<N, RB>;
+    __shared__ cf lds[RB * Lds<N>::LINE];
+    __shared__ float red[g::NT / kWave];
+    const int i = multi_find(m);
+    const BatchArgs a = m.tab[i];
+    const int local = (int)blockIdx.x - m.start[i];
+    stage_rows_fwd<N, RB>(a, local / g::G, local % g::G, lds, red);
+}
+
+template <int N>
+__global__ __launch_bounds__(kColNT<N>) void k_cols_multi(MultiArgs m) {
+    constexpr int CB = Tile<N>::CB;
+    using g = ColG<N, CB>;
+    __shared__ cf lds[CB * Lds<N>::LINE];
+    __shared__ double red[g::NT / kWave];
+    const int i = multi_find(m);
+    const BatchArgs a = m.tab[i];
+    const int local = (int)blockIdx.x - m.start[i];
+    stage_cols<N, CB>(a, local / g::GC, local % g::GC, lds, red);
+}
+
+template <int N>
+__global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
+    using g = InvG<N>;
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
+    __shared__ cf dl[g::S * g::R * N];
+    __shared__ float red[g::NT / kWave];
+    const int i = (int)blockIdx.x / g::GI;
+    const BatchArgs a = m.tab[i];
+    stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds, dl, red);
+}
+
 // Amplitude-loss forward (MODE kModeLoss: rows_fwd + cols only) and its
 // adjoint (kModeGrad: rows_fwd, cols, rows_inv accumulating the gradients).
 template <int N, int MODE>
@@ -538,6 +588,25 @@ hipError_t batch_n(const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
     return hipGetLastError();
 }
 
+template <int N>
+hipError_t batch_multi_n(const BatchArgs* dev_tab, const BatchArgs* host_tab, int count, hipStream_t s) {
+    using rg = RowG<N, Tile<N>::RB>;
+    using cg = ColG<N, Tile<N>::CB>;
+    if (count <= 0 || count > kMultiMax) return hipErrorInvalidValue;
+    MultiArgs mr{dev_tab, count, {}}, mc{dev_tab, count, {}};
+    mr.start[0] = mc.start[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        mr.start[i + 1] = mr.start[i] + rg::G * host_tab[i].bsize;
+        mc.start[i + 1] = mc.start[i] + cg::GC * host_tab[i].bsize;
+    }
+    if (mr.start[count] > 0) {
+        hipLaunchKernelGGL(k_rows_fwd_multi<N>, dim3(mr.start[count]), dim3(rg::NT), 0, s, mr);
+        hipLaunchKernelGGL(k_cols_multi<N>, dim3(mc.start[count]), dim3(cg::NT), 0, s, mc);
+    }
+    hipLaunchKernelGGL(k_rows_inv_multi<N>, dim3(InvG<N>::GI * count), dim3(InvG<N>::NT), 0, s, mr);
+    return hipGetLastError();
+}
+
 // refresh the partial maxima of |P|^2 in the layout of `form`
 template <int N>
 hipError_t probe_n(const BatchArgs& a, int form, hipStream_t s) {
@@ -627,6 +696,12 @@ hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev
 
 hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s) {
     PTYC_DISPATCH(n, probe_n<N>(a, form, s));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* host_tab, int count,
+                              hipStream_t s) {
+    PTYC_DISPATCH(n, batch_multi_n<N>(dev_tab, host_tab, count, s));
     return hipErrorInvalidValue;
 }
 

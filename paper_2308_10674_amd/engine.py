@@ -231,6 +231,22 @@ class Engine:
             pass
 
 
+def sweep_multi(engines, n_sweeps=1, errors=False):
+    """Run n_sweeps sweeps of several independent reconstructions together
+    (one launch per stage and pattern size covers the current batch of all
+    of them).  Same result as calling each engine's sweep(n_sweeps).
+    Returns an [len(engines), n_sweeps] array of errors when ``errors``."""
+    lib = L.lib()
+    arr = (C.c_void_p * len(engines))(*[e._ctx.value for e in engines])
+    err = np.zeros((len(engines), n_sweeps), dtype=np.float64) if errors else None
+    ep = err.ctypes.data_as(C.POINTER(C.c_double)) if errors else None
+    rc = lib.ptyc_sweep_multi(arr, len(engines), n_sweeps, ep)
+    if rc != L.PTYC_OK:
+        msgs = "; ".join(lib.ptyc_last_error(e._ctx).decode() for e in engines)
+        raise L.PtycError(rc, msgs or "ptyc_sweep_multi failed")
+    return err
+
+
 # ---------------------------------------------------------------- host helpers
 
 def colour(positions, n, max_batch=0):

@@ -1,0 +1,83 @@
+"""Several independent reconstructions advanced together (ptyc_sweep_multi):
+the same bytes as each context sweeping alone, and each context's batches
+re-synced to the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import sim
+from _parity import check_batches, engine_for, run_batches_resynced
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _scans():
+    """Five small scans of three pattern sizes, uneven position counts."""
+    out = []
+    for k, (n, side, count) in enumerate([(64, 9, 81), (128, 12, 140), (64, 7, 40), (256, 6, 36), (128, 5, 25)]):
+        step = max(1, int(round(0.094 * n)))
+        cen = np.stack(np.meshgrid(np.arange(side), np.arange(side), indexing="ij"), -1).reshape(-1, 2)[:count] * step
+        h, w, corners = sim.object_extent(cen, n, 32)
+        r = {64: 20.0, 128: 40.0, 256: 70.0}[n]
+        wl = sim.make_workload(n, None, r, 0.5 / r, corners, 1e7, 500 + k, h=h, w=w)
+        out.append(wl)
+    return out
+
+
+def test_multi_equals_individual_sweeps():
+    from paper_2308_10674_amd import sweep_multi
+    scans = _scans()
+    together = [engine_for(wl) for wl in scans]
+    alone = [engine_for(wl) for wl in scans]
+    empty = engine_for(scans[0], count=0)
+    err_m = sweep_multi(together + [empty], 3, errors=True)
+    for e_alone, e_tog, k in zip(alone, together, range(len(scans))):
+        err_a = e_alone.sweep(3, errors=True)
+        np.testing.assert_array_equal(e_tog.get_object(), e_alone.get_object())
+        np.testing.assert_array_equal(e_tog.get_probe(), e_alone.get_probe())
+        np.testing.assert_allclose(err_m[k], err_a, rtol=1e-13)
+        assert e_tog.sweeps_done == 3
+    np.testing.assert_array_equal(err_m[-1], 0.0)
+    # the next default schedules continue in step
+    for e_alone, e_tog in zip(alone, together):
+        oa, fa = e_alone.get_schedule()
+        ot, ft = e_tog.get_schedule()
+        np.testing.assert_array_equal(oa, ot)
+
+
+def test_multi_each_scan_matches_oracle():
+    """After a joint sweep, the next batch-by-batch sweep of every scan agrees
+    with the FP64 oracle (the joint call leaves per-scan state consistent)."""
+    from paper_2308_10674_amd import sweep_multi
+    scans = _scans()[:3]
+    engs = [engine_for(wl) for wl in scans]
+    sweep_multi(engs, 1)
+    for wl, eng in zip(scans, engs):
+        order, off = eng.get_schedule()
+        # start the oracle from the state the oracle itself reaches after the same first sweep
+        o0, f0 = _first_schedule(wl)
+        O1, P1, _, _ = oracle.sweep_coloured(wl.object0, wl.probe0, wl.positions, wl.intensities, o0, f0)
+        rows, _ = run_batches_resynced(eng, wl, order, off, start=(O1, P1), label=f"multi n{wl.n}")
+        check_batches(rows)
+
+
+def _first_schedule(wl):
+    e = engine_for(wl)
+    return e.get_schedule()
+
+
+def test_multi_rejects_bad_lists():
+    from paper_2308_10674_amd import PtycError, sweep_multi
+    scans = _scans()[:2]
+    a = engine_for(scans[0])
+    with pytest.raises(PtycError):
+        sweep_multi([a, a], 1)
+    with pytest.raises(PtycError):
+        sweep_multi([], 1)
