@@ -107,13 +107,50 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0,
  * the given order) with their diffraction intensities, while the
  * reconstruction continues ("Extensions of the ePIE implementation").
  * pos_yx: count*2 int32 (row, col) window corners; intensities:
- * count*N*N float32 (photon counts, or sqrt when PTYC_I_IS_SQRT), both in
+ * count raw frames of frame_h*frame_w float32 (N*N unless ptyc_set_ingest
+ * says otherwise; photon counts, or sqrt when PTYC_I_IS_SQRT), both in
  * mem_kind memory.  All or nothing: PTYC_ERR_BOUNDS if a window leaves the
  * object, PTYC_ERR_ARG if an intensity is negative or not finite; then
  * nothing is appended.  count == 0 is a no-op.  Extends the coloured
  * schedule incrementally (greedy first-fit, earlier batches unchanged). */
 int ptyc_add_positions(ptyc_ctx* ctx, int64_t count, const int32_t* pos_yx,
                        const float* intensities, int mem_kind);
+
+/* Preprocessing applied by add_positions to every raw detector frame (the
+ * paper's "ePIE Implementation" and "Preprocessing" sections: patterns are
+ * cropped to 2^n and rotated or flipped to match the handedness of the
+ * position encoders; its Discussion asks for masking invalid pixels).
+ * Frames are frame_h x frame_w float32; the n x n crop starting at
+ * (crop_y, crop_x) is kept; orient selects one of the 8 symmetries of the
+ * square (bit 0: transpose, then bit 1: flip rows, then bit 2: flip
+ * columns); PTYC_I_CENTERED moves DC from (n/2, n/2) to (0, 0); counts are
+ * multiplied by scale (a detector gain) before the square root
+ * (PTYC_I_IS_SQRT: the frames hold amplitudes, multiplied by sqrt(scale)).
+ * The default is frame n x n, crop (0, 0), orient 0, scale 1 and the flags
+ * of the config.  Must be called before set_mask and before any data.
+ * Errors: PTYC_ERR_ARG (crop outside the frame, orient not in 0..7, scale
+ * not finite and positive, unknown flags, reserved != 0, data present). */
+typedef struct ptyc_ingest {
+    int32_t frame_h, frame_w;
+    int32_t crop_y, crop_x;
+    int32_t orient;
+    float scale;
+    uint32_t flags;
+    int32_t reserved;   /* must be 0 */
+} ptyc_ingest;
+int ptyc_set_ingest(ptyc_ctx* ctx, const ptyc_ingest* spec);
+
+/* Detector mask in raw frame coordinates (frame_h * frame_w bytes, nonzero
+ * = a measured pixel), in mem_kind memory, copied.  At a masked pixel there
+ * is no measurement: the modulus replacement keeps the model's value there,
+ * the pixel adds nothing to the error metric or to the amplitude loss, and
+ * it is stored as 0.  Must be set before any data.  Errors: PTYC_ERR_ARG. */
+int ptyc_set_mask(ptyc_ctx* ctx, const uint8_t* mask, int mem_kind);
+
+/* Copy the stored amplitudes sqrt(I) of positions first .. first+count-1
+ * (count * N * N float32, after preprocessing) to mem_kind memory.
+ * Synchronises.  Errors: PTYC_ERR_ARG for a range outside the loaded data. */
+int ptyc_get_patterns(ptyc_ctx* ctx, int64_t first, int64_t count, float* out, int mem_kind);
 
 /* Run n_sweeps passes (iterations) over the loaded positions.
  * order == NULL: the library's schedule; each sweep draws a fresh random
@@ -147,6 +184,15 @@ int ptyc_sweep(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
  * repeated context, mixed streams, too many contexts). */
 #define PTYC_MULTI_MAX 64
 int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, double* err_out);
+
+/* Replace the object and the probe of each of n_ctx contexts by their mean
+ * over the contexts (summed in list order).  This is the synchronisation
+ * step of the paper's parallel processing scheme ("Simulating live and
+ * parallel processing": independent iterations on disjoint subsets of the
+ * data, with the object and the illumination averaged between them).  All
+ * contexts must share N, H, W, device and stream; n_ctx <= PTYC_MULTI_MAX.
+ * Errors: PTYC_ERR_ARG. */
+int ptyc_average(ptyc_ctx* const* ctxs, int32_t n_ctx);
 
 /* Export the schedule the next sweep with order == NULL would run:
  * order receives n_loaded indices, batch_offsets n_batches+1 offsets (host

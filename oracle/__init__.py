@@ -18,3 +18,5 @@ from .epie import (  # noqa: F401
     reconstruct,
 )
 from .adjoint import amplitude_loss, amplitude_loss_grad  # noqa: F401
+from .parallel import round_robin, subset_round  # noqa: F401
+from .ingest import orient_crop, preprocess  # noqa: F401

@@ -23,7 +23,7 @@ import numpy as np
 from .epie import fft2, ifft2, sgn
 
 
-def amplitude_loss(obj, probe, positions, intensities, idx=None):
+def amplitude_loss(obj, probe, positions, intensities, idx=None, mask=None):
     n = probe.shape[0]
     idx = range(len(positions)) if idx is None else idx
     total = 0.0
@@ -31,11 +31,12 @@ def amplitude_loss(obj, probe, positions, intensities, idx=None):
         y, x = int(positions[j][0]), int(positions[j][1])
         Psi = fft2(probe * obj[y:y + n, x:x + n])
         a = np.sqrt(np.asarray(intensities[j], dtype=np.float64))
-        total += float(np.sum((np.abs(Psi) - a) ** 2))
+        r = (np.abs(Psi) - a) ** 2
+        total += float(np.sum(r if mask is None else np.where(mask, r, 0.0)))
     return total
 
 
-def amplitude_loss_grad(obj, probe, positions, intensities, idx=None):
+def amplitude_loss_grad(obj, probe, positions, intensities, idx=None, mask=None):
     """Returns (loss, grad_O, grad_P) in complex128."""
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
@@ -50,6 +51,8 @@ def amplitude_loss_grad(obj, probe, positions, intensities, idx=None):
         Psi = fft2(probe * win)
         a = np.sqrt(np.asarray(intensities[j], dtype=np.float64))
         r = np.abs(Psi) - a
+        if mask is not None:
+            r = np.where(mask, r, 0.0)   # no measurement: no loss, no gradient
         total += float(np.sum(r ** 2))
         g_psi = (n * n) * ifft2(2.0 * r * sgn(Psi))
         g_o[y:y + n, x:x + n] += np.conj(probe) * g_psi

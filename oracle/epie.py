@@ -88,21 +88,33 @@ def exit_wave(probe, obj, yx):
     return probe * obj[y:y + n, x:x + n]
 
 
-def modulus_replace(Psi, sqrt_i):
-    """Psi' = sqrt(I) * sgn(Psi): keep the phase, impose the measured modulus."""
-    return sqrt_i * sgn(Psi)
+def modulus_replace(Psi, sqrt_i, mask=None):
+    """Psi' = sqrt(I) * sgn(Psi): keep the phase, impose the measured modulus.
+    Where ``mask`` is False there is no measurement and Psi' = Psi."""
+    out = sqrt_i * sgn(Psi)
+    if mask is not None:
+        out = np.where(mask, out, Psi)
+    return out
 
 
-def position_update(probe, win, sqrt_i, alpha):
+def _err(Psi, sqrt_i, mask):
+    r = (np.abs(Psi) - sqrt_i) ** 2
+    if mask is not None:
+        r = np.where(mask, r, 0.0)
+    return r
+
+
+def position_update(probe, win, sqrt_i, alpha, mask=None):
     """One ePIE position update from pre-update values.
 
     Returns (new window, probe increment d, error term) where the caller
     applies P <- P + beta * d (sequential) or averages d over a batch.
+    ``mask`` (bool, N x N) marks measured detector pixels.
     """
     psi = probe * win
     Psi = fft2(psi)
-    err = float(np.sum((np.abs(Psi) - sqrt_i) ** 2))
-    psi_new = ifft2(modulus_replace(Psi, sqrt_i))
+    err = float(np.sum(_err(Psi, sqrt_i, mask)))
+    psi_new = ifft2(modulus_replace(Psi, sqrt_i, mask))
     delta = psi_new - psi
     pmax = np.max(np.abs(probe) ** 2)
     omax = np.max(np.abs(win) ** 2)
@@ -121,7 +133,7 @@ def _prep(obj, probe, intensities, dtype):
 
 
 def sweep_strict(obj, probe, positions, intensities, order, alpha=1.0,
-                 beta=1.0, dtype=np.complex128):
+                 beta=1.0, dtype=np.complex128, mask=None):
     """One sequential ePIE sweep over ``order``.
 
     Returns (object, probe, error numerator, error denominator)."""
@@ -132,7 +144,7 @@ def sweep_strict(obj, probe, positions, intensities, order, alpha=1.0,
     for j in order:
         y, x = int(positions[j][0]), int(positions[j][1])
         win = O[y:y + n, x:x + n].copy()
-        new_win, d, e = position_update(P, win, sq[j], alpha)
+        new_win, d, e = position_update(P, win, sq[j], alpha, mask)
         O[y:y + n, x:x + n] = new_win
         P = P + beta * d
         num += e
@@ -141,7 +153,7 @@ def sweep_strict(obj, probe, positions, intensities, order, alpha=1.0,
 
 
 def sweep_coloured(obj, probe, positions, intensities, order, batch_offsets,
-                   alpha=1.0, beta=1.0, dtype=np.complex128, check=True):
+                   alpha=1.0, beta=1.0, dtype=np.complex128, check=True, mask=None):
     """One coloured-batch sweep: batches order[off[b]:off[b+1]] in turn.
 
     Within a batch every position uses the batch's probe P_b; the windows
@@ -171,9 +183,9 @@ def sweep_coloured(obj, probe, positions, intensities, order, batch_offsets,
         psi = P[None] * win
         Psi = fft2(psi)
         a = sq[idx]
-        num += float(np.sum((np.abs(Psi).astype(np.float64) - a) ** 2))
+        num += float(np.sum(_err(np.abs(Psi).astype(np.float64), a, mask)))
         den += float(np.sum(np.asarray(intensities[idx], dtype=np.float64)))
-        delta = ifft2(modulus_replace(Psi, a)) - psi
+        delta = ifft2(modulus_replace(Psi, a, mask)) - psi
         pmax = np.max(np.abs(P) ** 2).astype(pmax_dtype)
         omax = np.max(np.abs(win) ** 2, axis=(1, 2)).astype(pmax_dtype)
         O[rows, cols] = win + alpha * np.conj(P)[None] * delta / pmax
@@ -271,7 +283,7 @@ def rel_l2(x, ref, mask=None):
 
 
 def reconstruct(obj, probe, positions, intensities, schedules, alpha=1.0,
-                beta=1.0, dtype=np.complex128):
+                beta=1.0, dtype=np.complex128, mask=None):
     """Run a list of sweeps.  Each schedule entry is (order, batch_offsets)
     for a coloured sweep or (order, None) for a sequential one.
     Returns (object, probe, [E per sweep])."""
@@ -280,9 +292,9 @@ def reconstruct(obj, probe, positions, intensities, schedules, alpha=1.0,
     for order, off in schedules:
         if off is None:
             O, P, num, den = sweep_strict(O, P, positions, intensities, order,
-                                          alpha, beta, dtype)
+                                          alpha, beta, dtype, mask=mask)
         else:
             O, P, num, den = sweep_coloured(O, P, positions, intensities, order,
-                                            off, alpha, beta, dtype)
+                                            off, alpha, beta, dtype, mask=mask)
         errs.append(num / den if den > 0 else 0.0)
     return O, P, errs

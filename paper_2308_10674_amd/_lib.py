@@ -43,6 +43,13 @@ class Config(C.Structure):
     ]
 
 
+class Ingest(C.Structure):
+    _fields_ = [
+        ("frame_h", C.c_int32), ("frame_w", C.c_int32), ("crop_y", C.c_int32), ("crop_x", C.c_int32),
+        ("orient", C.c_int32), ("scale", C.c_float), ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
 _P = C.c_void_p
 _I64P = C.POINTER(C.c_int64)
 _I32P = C.POINTER(C.c_int32)
@@ -53,7 +60,11 @@ SIGNATURES = {
     "ptyc_add_positions": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int]),
     "ptyc_sweep": (C.c_int, [_P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64, _DP]),
     "ptyc_sweep_multi": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP]),
+    "ptyc_average": (C.c_int, [C.POINTER(_P), C.c_int32]),
     "ptyc_get_schedule": (C.c_int, [_P, _I64P, _I64P, _I64P]),
+    "ptyc_set_ingest": (C.c_int, [_P, C.POINTER(Ingest)]),
+    "ptyc_set_mask": (C.c_int, [_P, _P, C.c_int]),
+    "ptyc_get_patterns": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int]),
     "ptyc_get_object": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_get_probe": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_set_object": (C.c_int, [_P, _P, C.c_int]),

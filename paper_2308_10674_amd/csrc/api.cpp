@@ -49,6 +49,8 @@ struct ptyc_ctx {
     DevBuf bad;                      // int flag for ingest validation
     DevBuf sync;                     // [0] barrier counter, [1] barrier fault flag
     DevBuf multi;                    // batch descriptors of a multi-context call
+    DevBuf mask;                     // uint8 [n][n] measured detector pixels (stored layout), if set
+    ptyc_ingest ingest{};            // how raw frames become stored amplitudes
     DevBuf staging;                  // host intensities staged on the device
 
     // host state
@@ -206,7 +208,36 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.err_part = (double*)c->err_part.p;
     a.alpha = c->cfg.alpha;
     a.beta = c->cfg.beta;
+    a.mask = (const unsigned char*)c->mask.p;
     return a;
+}
+
+IngestSpec ingest_spec(const ptyc_ctx* c) {
+    IngestSpec sp{};
+    sp.frame_h = c->ingest.frame_h;
+    sp.frame_w = c->ingest.frame_w;
+    sp.crop_y = c->ingest.crop_y;
+    sp.crop_x = c->ingest.crop_x;
+    sp.orient = c->ingest.orient;
+    sp.centred = (c->ingest.flags & PTYC_I_CENTERED) != 0;
+    sp.is_sqrt = (c->ingest.flags & PTYC_I_IS_SQRT) != 0;
+    sp.scale = c->ingest.scale;
+    sp.mask = (const unsigned char*)c->mask.p;
+    return sp;
+}
+
+// stored-layout pixel (a, b) of crop pixel (r, c), as the ingest kernel maps it
+void ingest_map(const ptyc_ingest& g, int n, int r, int cc, int* a, int* b) {
+    int y = r, x = cc;
+    if (g.orient & 1) std::swap(y, x);
+    if (g.orient & 2) y = n - 1 - y;
+    if (g.orient & 4) x = n - 1 - x;
+    if (g.flags & PTYC_I_CENTERED) {
+        y = (y + n / 2) % n;
+        x = (x + n / 2) % n;
+    }
+    *a = y;
+    *b = x;
 }
 
 int copy_square_in(ptyc_ctx* c, DevBuf& dst, const void* src, size_t bytes, int kind) {
@@ -296,6 +327,9 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     c->sp = shape_for(cfg->n, kFormPersistent);
     c->dev_limit = env_limit();
     c->colouring = new Colouring(cfg->n, max_batch_of(c));
+    c->ingest.frame_h = c->ingest.frame_w = cfg->n;
+    c->ingest.scale = 1.0f;
+    c->ingest.flags = cfg->flags;
     (void)hipGetDevice(&c->device);
 
     const int n = cfg->n;
@@ -340,7 +374,7 @@ void ptyc_destroy(ptyc_ctx* c) {
     if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
                       &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
-                      &c->err_dev, &c->bad, &c->sync, &c->multi, &c->staging};
+                      &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging};
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -434,23 +468,23 @@ int ptyc_add_positions(ptyc_ctx* c, int64_t count, const int32_t* pos_yx, const 
         c->cap = ncap;
     }
     HIPCHK(c, hipMemsetAsync(c->bad.p, 0, sizeof(int), c->stream));
-    const bool is_sqrt = (c->cfg.flags & PTYC_I_IS_SQRT) != 0;
-    const bool centred = (c->cfg.flags & PTYC_I_CENTERED) != 0;
+    const IngestSpec sp = ingest_spec(c);
+    const size_t fsz = (size_t)sp.frame_h * sp.frame_w;   // floats per raw frame
     float* dst = (float*)c->sqrt_i.p + (size_t)first * nn;
     double* sdst = (double*)c->sum_i.p + first;
     if (mem_kind == PTYC_MEM_DEVICE) {
-        HIPCHK(c, launch_ingest(n, inten, dst, sdst, count, is_sqrt, centred, (int*)c->bad.p, c->stream));
+        HIPCHK(c, launch_ingest(n, inten, dst, sdst, count, sp, (int*)c->bad.p, c->stream));
     } else {
         // stage through a bounded device buffer
-        const int64_t chunk = std::max<int64_t>(1, (int64_t)((size_t)(64u << 20) / (nn * sizeof(float))));
+        const int64_t chunk = std::max<int64_t>(1, (int64_t)((size_t)(64u << 20) / (fsz * sizeof(float))));
         const int64_t cn = std::min(chunk, count);
-        if ((rc = ensure(c, c->staging, (size_t)cn * nn * sizeof(float))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->staging, (size_t)cn * fsz * sizeof(float))) != PTYC_OK) return rc;
         for (int64_t a = 0; a < count; a += cn) {
             const int64_t m = std::min(cn, count - a);
-            HIPCHK(c, hipMemcpyAsync(c->staging.p, inten + (size_t)a * nn, (size_t)m * nn * sizeof(float),
+            HIPCHK(c, hipMemcpyAsync(c->staging.p, inten + (size_t)a * fsz, (size_t)m * fsz * sizeof(float),
                                      hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, launch_ingest(n, (const float*)c->staging.p, dst + (size_t)a * nn, sdst + a, m, is_sqrt,
-                                    centred, (int*)c->bad.p, c->stream));
+            HIPCHK(c, launch_ingest(n, (const float*)c->staging.p, dst + (size_t)a * nn, sdst + a, m, sp,
+                                    (int*)c->bad.p, c->stream));
         }
     }
     std::vector<int2> pd((size_t)count);
@@ -464,6 +498,64 @@ int ptyc_add_positions(ptyc_ctx* c, int64_t count, const int32_t* pos_yx, const 
     c->h_pos.insert(c->h_pos.end(), p.begin(), p.end());
     c->colouring->extend(c->h_pos.data(), first, count);
     c->n_loaded = total;
+    return PTYC_OK;
+}
+
+int ptyc_set_ingest(ptyc_ctx* c, const ptyc_ingest* g) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!g) return fail(c, PTYC_ERR_ARG, "spec is NULL");
+    if (c->n_loaded > 0 || c->mask.p) return fail(c, PTYC_ERR_ARG, "set the ingest spec before the mask and any data");
+    const int n = c->cfg.n;
+    if (g->frame_h < n || g->frame_w < n || g->crop_y < 0 || g->crop_x < 0 || g->crop_y > g->frame_h - n ||
+        g->crop_x > g->frame_w - n)
+        return fail(c, PTYC_ERR_ARG, "the n x n crop must lie inside the frame");
+    if (g->orient < 0 || g->orient > 7) return fail(c, PTYC_ERR_ARG, "orient must be in 0..7");
+    if (!(g->scale > 0.f) || !std::isfinite(g->scale)) return fail(c, PTYC_ERR_ARG, "scale must be finite and > 0");
+    if (g->flags & ~(PTYC_I_IS_SQRT | PTYC_I_CENTERED)) return fail(c, PTYC_ERR_ARG, "unknown flag bits");
+    if (g->reserved != 0) return fail(c, PTYC_ERR_ARG, "reserved must be 0");
+    c->ingest = *g;
+    return PTYC_OK;
+}
+
+int ptyc_set_mask(ptyc_ctx* c, const uint8_t* mask, int kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!mask || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad mask buffer or mem_kind");
+    if (c->n_loaded > 0) return fail(c, PTYC_ERR_ARG, "set the mask before adding data");
+    const ptyc_ingest& g = c->ingest;
+    const size_t fsz = (size_t)g.frame_h * g.frame_w;
+    std::vector<uint8_t> raw(fsz);
+    if (kind == PTYC_MEM_HOST) {
+        std::memcpy(raw.data(), mask, fsz);
+    } else {
+        HIPCHK(c, hipMemcpyAsync(raw.data(), mask, fsz, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    const int n = c->cfg.n;
+    std::vector<uint8_t> m((size_t)n * n, 0);
+    for (int r = 0; r < n; ++r)
+        for (int cc = 0; cc < n; ++cc) {
+            int a, b;
+            ingest_map(g, n, r, cc, &a, &b);
+            m[(size_t)a * n + b] = raw[(size_t)(g.crop_y + r) * g.frame_w + g.crop_x + cc] ? 1 : 0;
+        }
+    if ((rc = ensure(c, c->mask, m.size())) != PTYC_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->mask.p, m.data(), m.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
+int ptyc_get_patterns(ptyc_ctx* c, int64_t first, int64_t count, float* out, int kind) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (first < 0 || count < 0 || first + count > c->n_loaded) return fail(c, PTYC_ERR_ARG, "range outside the loaded positions");
+    if (count == 0) return PTYC_OK;
+    if (!out || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad output buffer or mem_kind");
+    const size_t nn = (size_t)c->cfg.n * c->cfg.n;
+    HIPCHK(c, hipMemcpyAsync(out, (const float*)c->sqrt_i.p + (size_t)first * nn, (size_t)count * nn * sizeof(float),
+                             from_dev(kind), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PTYC_OK;
 }
 
@@ -782,6 +874,36 @@ int ptyc_set_probe(ptyc_ctx* c, const void* in, int kind) {
     if (!in || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad input buffer or mem_kind");
     if ((rc = copy_square_in(c, c->probe, in, (size_t)c->cfg.n * c->cfg.n * sizeof(cf), kind)) != PTYC_OK) return rc;
     return refresh_probe_max(c);
+}
+
+int ptyc_average(ptyc_ctx* const* ctxs, int32_t n_ctx) {
+    if (!ctxs || n_ctx <= 0 || n_ctx > PTYC_MULTI_MAX) return PTYC_ERR_ARG;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return PTYC_ERR_ARG;
+        int rc = usable(ctxs[i]);
+        if (rc) return rc;
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) return fail(ctxs[i], PTYC_ERR_ARG, "a context appears twice");
+        const ptyc_config& a = ctxs[0]->cfg;
+        const ptyc_config& b = ctxs[i]->cfg;
+        if (a.n != b.n || a.h != b.h || a.w != b.w)
+            return fail(ctxs[i], PTYC_ERR_ARG, "all contexts must share pattern and object size");
+        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device)
+            return fail(ctxs[i], PTYC_ERR_ARG, "all contexts must share one device and stream");
+    }
+    ptyc_ctx* c0 = ctxs[0];
+    std::vector<void*> o((size_t)n_ctx), p((size_t)n_ctx);
+    for (int i = 0; i < n_ctx; ++i) {
+        o[(size_t)i] = ctxs[i]->obj.p;
+        p[(size_t)i] = ctxs[i]->probe.p;
+    }
+    HIPCHK(c0, launch_mean(o.data(), n_ctx, (int64_t)c0->cfg.h * c0->cfg.w, c0->stream));
+    HIPCHK(c0, launch_mean(p.data(), n_ctx, (int64_t)c0->cfg.n * c0->cfg.n, c0->stream));
+    for (int i = 0; i < n_ctx; ++i) {
+        int rc = refresh_probe_max(ctxs[i]);
+        if (rc) return rc;
+    }
+    return PTYC_OK;
 }
 
 int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,

@@ -30,6 +30,18 @@ struct BatchArgs {
     cf* gobj;                 // amplitude-loss gradient w.r.t. the object (accumulated)
     cf* gprobe;               // amplitude-loss gradient w.r.t. the probe (accumulated)
     float gscale;             // upstream scale of the gradient
+    const unsigned char* mask;  // [n][n] 1 = measured detector pixel; nullptr: all measured
+};
+
+// How raw detector frames become stored amplitudes.
+struct IngestSpec {
+    int frame_h, frame_w;     // raw frame size
+    int crop_y, crop_x;       // top-left corner of the n x n crop in the frame
+    int orient;               // bit 0 transpose, bit 1 flip rows, bit 2 flip columns
+    int centred;              // the crop has DC at (n/2, n/2)
+    int is_sqrt;              // frames hold amplitudes, not counts
+    float scale;              // counts are multiplied by scale
+    const unsigned char* mask;  // [n][n] in the stored layout, or nullptr
 };
 
 // What the column and inverse-row stages compute.
@@ -74,10 +86,11 @@ hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_ba
 // dL/dO into gobj and dL/dP into gprobe
 hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s);
+// replace each of the k arrays (count_c64 complex values each) by their mean
+hipError_t launch_mean(void* const* ptrs, int k, int64_t count_c64, hipStream_t s);
 hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hipStream_t s);
 hipError_t launch_ingest(int n, const float* src, float* sqrt_i_dst, double* sum_i_dst,
-                         int64_t count, bool is_sqrt, bool centred, int* bad_flag,
-                         hipStream_t s);
+                         int64_t count, const IngestSpec& spec, int* bad_flag, hipStream_t s);
 hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const int64_t* order,
                              int64_t order_len, const double* sum_i, double* err_out,
                              hipStream_t s);

@@ -200,11 +200,15 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
     float amp[g::N1];
 #pragma unroll
     for (int n1 = 0; n1 < g::N1; ++n1) v[n1] = base[(size_t)(g::N2 * n1 + t) * N];
+    bool valid[g::N1];
 #pragma unroll
     for (int mm = 0; mm < g::N1 / g::N2; ++mm)
 #pragma unroll
-        for (int k2 = 0; k2 < g::N2; ++k2)
-            amp[mm * g::N2 + k2] = ampb[(size_t)((t + g::N2 * mm) + g::N1 * k2) * N];
+        for (int k2 = 0; k2 < g::N2; ++k2) {
+            const int row = (t + g::N2 * mm) + g::N1 * k2;
+            amp[mm * g::N2 + k2] = ampb[(size_t)row * N];
+            valid[mm * g::N2 + k2] = a.mask == nullptr || a.mask[row * N + c] != 0;
+        }
     cf* z = lds + cl * Lds<N>::LINE;
     passA_to_lds<N, -1>(v, z, t, a.tw);
     __syncthreads();
@@ -216,6 +220,12 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
         const cf zz = v[i];
         const float mag = sqrtf(norm2(zz));
         const float d = mag - s;
+        if (!valid[i]) {
+            // a masked detector pixel: no measurement, so the model's value
+            // stays (ePIE) and it carries no loss (gradient)
+            if (MODE == kModeGrad) v[i] = cf{0.f, 0.f};
+            continue;
+        }
         e += d * d;
         if (MODE == kModeEpie) {
             // Psi' = sqrt(I) sgn(Psi)
@@ -429,6 +439,24 @@ __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
     stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds, dl, red);
 }
 
+// Mean of K equally shaped complex arrays, written back to all of them
+// (summed in list order, so the result does not depend on the launch).
+struct MeanArgs {
+    cf* ptr[kMultiMax];
+    int k;
+    int64_t count;
+};
+
+__global__ __launch_bounds__(256) void k_mean(MeanArgs m) {
+    const float inv = 1.f / (float)m.k;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m.count; e += (int64_t)gridDim.x * 256) {
+        cf acc = m.ptr[0][e];
+        for (int i = 1; i < m.k; ++i) acc = acc + m.ptr[i][e];
+        acc = inv * acc;
+        for (int i = 0; i < m.k; ++i) m.ptr[i][e] = acc;
+    }
+}
+
 // Amplitude-loss forward (MODE kModeLoss: rows_fwd + cols only) and its
 // adjoint (kModeGrad: rows_fwd, cols, rows_inv accumulating the gradients).
 template <int N, int MODE>
@@ -523,26 +551,42 @@ __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 // ---------------------------------------------------------------- ingest
 template <int N>
-__global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ src, float* dst,
-                                                double* sum_i, int is_sqrt, int centred,
-                                                int* bad) {
+__global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ src, float* dst, double* sum_i,
+                                                IngestSpec sp, int* bad) {
     __shared__ double red[256 / kWave];
     const size_t i = blockIdx.x;
-    const float* s = src + i * N * N;
+    const float* f = src + i * (size_t)sp.frame_h * sp.frame_w;
     float* d = dst + i * N * N;
+    const float rs = sqrtf(sp.scale);
     double acc = 0.0;
     int badl = 0;
     for (int e = threadIdx.x; e < N * N; e += 256) {
-        const float x = s[e];
-        if (!(x >= 0.f) || !isfinite(x)) badl = 1;
-        const float amp = is_sqrt ? x : sqrtf(x);
-        acc += is_sqrt ? (double)x * (double)x : (double)x;
-        int r = e / N, c = e % N;
-        if (centred) {
-            r = (r + N / 2) % N;
-            c = (c + N / 2) % N;
+        const int r = e / N, c = e % N;   // pixel of the N x N crop
+        const float x = f[(size_t)(sp.crop_y + r) * sp.frame_w + sp.crop_x + c];
+        // orientation (transpose, then row flip, then column flip), then the
+        // optional move of DC from (N/2, N/2) to (0, 0)
+        int a = r, b = c;
+        if (sp.orient & 1) { const int t = a; a = b; b = t; }
+        if (sp.orient & 2) a = N - 1 - a;
+        if (sp.orient & 4) b = N - 1 - b;
+        if (sp.centred) {
+            a = (a + N / 2) % N;
+            b = (b + N / 2) % N;
         }
-        d[r * N + c] = amp;
+        const bool valid = sp.mask == nullptr || sp.mask[a * N + b] != 0;
+        float amp = 0.f;
+        if (valid) {
+            if (!(x >= 0.f) || !isfinite(x)) badl = 1;
+            if (sp.is_sqrt) {
+                amp = x * rs;
+                acc += (double)amp * (double)amp;
+            } else {
+                const float v = sp.scale * x;
+                amp = sqrtf(v);
+                acc += (double)v;
+            }
+        }
+        d[a * N + b] = amp;
     }
     if (badl) atomicOr(bad, 1);
     const double tot = block_sum<256>(acc, red);
@@ -663,11 +707,10 @@ hipError_t sweep_n(const BatchArgs& a, const SweepCtl& c, int max_batch, hipStre
 }
 
 template <int N>
-hipError_t ingest_n(const float* src, float* dst, double* sum_i, int64_t count, bool is_sqrt,
-                    bool centred, int* bad, hipStream_t s) {
+hipError_t ingest_n(const float* src, float* dst, double* sum_i, int64_t count, const IngestSpec& sp, int* bad,
+                    hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ingest<N>, dim3((unsigned)count), dim3(256), 0, s, src, dst, sum_i,
-                       (int)is_sqrt, (int)centred, bad);
+    hipLaunchKernelGGL(k_ingest<N>, dim3((unsigned)count), dim3(256), 0, s, src, dst, sum_i, sp, bad);
     return hipGetLastError();
 }
 
@@ -705,6 +748,17 @@ hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* 
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_mean(void* const* ptrs, int k, int64_t count_c64, hipStream_t s) {
+    if (k <= 0 || k > kMultiMax || count_c64 <= 0) return hipErrorInvalidValue;
+    MeanArgs m{};
+    for (int i = 0; i < k; ++i) m.ptr[i] = (cf*)ptrs[i];
+    m.k = k;
+    m.count = count_c64;
+    const int64_t blocks = std::min<int64_t>((count_c64 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_mean, dim3((unsigned)blocks), dim3(256), 0, s, m);
+    return hipGetLastError();
+}
+
 int persistent_capacity(int n) {
     PTYC_DISPATCH(n, persistent_capacity_n<N>());
     return 0;
@@ -734,8 +788,8 @@ hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hi
 }
 
 hipError_t launch_ingest(int n, const float* src, float* dst, double* sum_i, int64_t count,
-                         bool is_sqrt, bool centred, int* bad, hipStream_t s) {
-    PTYC_DISPATCH(n, ingest_n<N>(src, dst, sum_i, count, is_sqrt, centred, bad, s));
+                         const IngestSpec& sp, int* bad, hipStream_t s) {
+    PTYC_DISPATCH(n, ingest_n<N>(src, dst, sum_i, count, sp, bad, s));
     return hipErrorInvalidValue;
 }
 

@@ -106,6 +106,29 @@ class Engine:
         _check(lib.ptyc_add_positions(self._ctx, count, pp, ip, ik), self._ctx)
         return self
 
+    def set_ingest(self, frame=None, crop=(0, 0), orient=0, scale=1.0, centred=False, sqrt_input=False):
+        """Preprocessing of raw frames (see ptyc_set_ingest): frame size,
+        top-left corner of the n x n crop, orientation 0..7 (bit 0
+        transpose, bit 1 flip rows, bit 2 flip columns), gain scale, DC at
+        the crop centre, amplitudes instead of counts."""
+        fh, fw = (self.n, self.n) if frame is None else frame
+        spec = L.Ingest(frame_h=fh, frame_w=fw, crop_y=crop[0], crop_x=crop[1], orient=orient, scale=scale,
+                        flags=(L.PTYC_I_IS_SQRT if sqrt_input else 0) | (L.PTYC_I_CENTERED if centred else 0),
+                        reserved=0)
+        _check(L.lib().ptyc_set_ingest(self._ctx, C.byref(spec)), self._ctx)
+
+    def set_mask(self, mask):
+        """Detector mask in raw frame coordinates (nonzero = measured)."""
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        _check(L.lib().ptyc_set_mask(self._ctx, m.ctypes.data, L.PTYC_MEM_HOST), self._ctx)
+
+    def get_patterns(self, first=0, count=None):
+        """Stored amplitudes sqrt(I) after preprocessing, [count, n, n]."""
+        count = self.num_positions - first if count is None else count
+        out = np.empty((count, self.n, self.n), dtype=np.float32)
+        _check(L.lib().ptyc_get_patterns(self._ctx, first, count, out.ctypes.data, L.PTYC_MEM_HOST), self._ctx)
+        return out
+
     # ----------------------------------------------------------------- sweep
     def sweep(self, n_sweeps=1, order=None, batch_offsets=None, errors=False):
         """Run sweeps; returns the running Fourier error per sweep when
@@ -245,6 +268,17 @@ def sweep_multi(engines, n_sweeps=1, errors=False):
         msgs = "; ".join(lib.ptyc_last_error(e._ctx).decode() for e in engines)
         raise L.PtycError(rc, msgs or "ptyc_sweep_multi failed")
     return err
+
+
+def average(engines):
+    """Replace object and probe of every engine by their mean over the
+    engines (the synchronisation of the subset-parallel scheme)."""
+    lib = L.lib()
+    arr = (C.c_void_p * len(engines))(*[e._ctx.value for e in engines])
+    rc = lib.ptyc_average(arr, len(engines))
+    if rc != L.PTYC_OK:
+        msgs = "; ".join(lib.ptyc_last_error(e._ctx).decode() for e in engines)
+        raise L.PtycError(rc, msgs or "ptyc_average failed")
 
 
 # ---------------------------------------------------------------- host helpers

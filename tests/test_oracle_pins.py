@@ -372,3 +372,117 @@ def test_strict_sweep_beta_and_alpha():
     np.testing.assert_array_equal(P0, wl.probe0)
     O0, _, _, _ = oracle.sweep_strict(wl.object0, wl.probe0, wl.positions, wl.intensities, [0, 1, 2], alpha=0.0)
     np.testing.assert_array_equal(O0, wl.object0)
+
+
+# ------------------------------------------------------------- subset-parallel scheme
+
+def test_parallel_one_subset_is_plain_reconstruction():
+    wl = _tiny_problem(noise=True)
+    sched = [(sim.sweep_order(wl.seed, s, wl.count), None) for s in range(2)]
+    O1, P1, _ = oracle.reconstruct(wl.object0, wl.probe0, wl.positions, wl.intensities, sched)
+    O2, P2, _ = oracle.subset_round(wl.object0, wl.probe0, wl.positions, wl.intensities,
+                                    [np.arange(wl.count)], [sched])
+    np.testing.assert_array_equal(O1, O2)
+    np.testing.assert_array_equal(P1, P2)
+
+
+def test_parallel_separated_subsets_move_by_one_over_k():
+    """beta = 0 and subsets whose windows never meet: each subset's region
+    moves by exactly 1/K of what that subset alone does to it."""
+    n = 16
+    left = sim.raster_positions(3, 4, n, 40, 0, 1)                 # corners within [12, 20]
+    right = left + np.array([0, 60], dtype=np.int32)
+    pos = np.concatenate([left, right])
+    wl = sim.make_workload(n, 48, 4.0, 0.05, pos, 1e6, 13, noise=True, h=48, w=110)
+    subsets = [np.arange(9), np.arange(9, 18)]
+    sched = [[(np.arange(9)[::-1], None)], [(np.arange(9), None)]]
+    O, P, _ = oracle.subset_round(wl.object0, wl.probe0, wl.positions, wl.intensities, subsets, sched, beta=0.0)
+    np.testing.assert_array_equal(P, wl.probe0)
+    for sub, sc in zip(subsets, sched):
+        Ok, _, _ = oracle.reconstruct(wl.object0, wl.probe0, wl.positions[sub], wl.intensities[sub], sc, beta=0.0)
+        m = oracle.union_mask(wl.positions[sub], n, wl.h, wl.w)
+        np.testing.assert_allclose(O[m], wl.object0[m] + (Ok[m] - wl.object0[m]) / 2, atol=1e-14)
+
+
+def test_parallel_identical_subsets_average_to_one_run():
+    wl = _tiny_problem(noise=True)
+    sched = [(sim.sweep_order(wl.seed, 0, wl.count), None)]
+    O1, P1, _ = oracle.reconstruct(wl.object0, wl.probe0, wl.positions, wl.intensities, sched)
+    sub = np.arange(wl.count)
+    O3, P3, _ = oracle.subset_round(wl.object0, wl.probe0, wl.positions, wl.intensities, [sub] * 4, [sched] * 4)
+    np.testing.assert_allclose(O3, O1, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(P3, P1, rtol=0, atol=1e-13 * np.abs(P1).max())
+
+
+def test_round_robin_split():
+    subs = oracle.round_robin(10, 4)
+    assert [list(s) for s in subs] == [[0, 4, 8], [1, 5, 9], [2, 6], [3, 7]]
+
+
+# ------------------------------------------------------------- preprocessing and masks
+
+@pytest.mark.parametrize("orient,expect", [
+    (0, (3, 5)), (1, (5, 3)), (2, (4, 5)), (4, (3, 2)), (3, (2, 3)), (7, (2, 4)),
+])
+def test_preprocess_moves_a_single_pixel_where_stated(orient, expect):
+    """A bright pixel at crop position (3, 5) of an 8 x 8 crop lands where
+    transpose-then-flip-rows-then-flip-columns puts it (worked by hand)."""
+    frame = np.zeros((1, 20, 30))
+    frame[0, 6 + 3, 11 + 5] = 9.0
+    I, _ = oracle.preprocess(frame, 8, crop=(6, 11), orient=orient, scale=2.0)
+    assert I.shape == (1, 8, 8)
+    assert np.argwhere(I[0] == 18.0).tolist() == [list(expect)]
+    assert I.sum() == 18.0
+
+
+def test_preprocess_centred_moves_dc_to_origin():
+    frame = np.zeros((1, 8, 8))
+    frame[0, 4, 4] = 1.0
+    I, _ = oracle.preprocess(frame, 8, centred=True)
+    assert I[0, 0, 0] == 1.0
+
+
+def test_orientations_are_the_eight_symmetries():
+    a = np.arange(16.0).reshape(4, 4)
+    outs = {oracle.orient_crop(a, o, False).tobytes() for o in range(8)}
+    assert len(outs) == 8
+    np.testing.assert_array_equal(oracle.orient_crop(oracle.orient_crop(a, 1, False), 1, False), a)
+
+
+def test_mask_follows_the_data_and_zeroes_masked_pixels():
+    rng = np.random.default_rng(12)
+    frames = rng.random((2, 12, 12)) + 1
+    mask = np.ones((12, 12), bool)
+    mask[4, 7] = False
+    I, m = oracle.preprocess(frames, 8, crop=(2, 3), orient=5, centred=True, mask=mask)
+    J, _ = oracle.preprocess(frames, 8, crop=(2, 3), orient=5, centred=True)
+    assert (~m).sum() == 1
+    assert np.all(I[:, ~m] == 0) and np.all(I[:, m] == J[:, m])
+    marker = np.zeros((1, 12, 12))
+    marker[0, 4, 7] = 1
+    K, _ = oracle.preprocess(marker, 8, crop=(2, 3), orient=5, centred=True)
+    assert np.array_equal(K[0] == 1, ~m)
+
+
+def test_masked_modulus_projection():
+    rng = np.random.default_rng(13)
+    Psi = _rand_c(rng, (8, 8))
+    a = rng.random((8, 8)) + 0.5
+    m = rng.random((8, 8)) > 0.3
+    out = oracle.modulus_replace(Psi, a, m)
+    np.testing.assert_allclose(np.abs(out[m]), a[m], rtol=1e-14)
+    np.testing.assert_array_equal(out[~m], Psi[~m])
+
+
+def test_full_mask_is_no_mask_and_empty_mask_changes_nothing():
+    wl = _tiny_problem(noise=True)
+    order = sim.sweep_order(wl.seed, 0, wl.count)
+    ones = np.ones((wl.n, wl.n), bool)
+    O1, P1, n1, _ = oracle.sweep_strict(wl.object0, wl.probe0, wl.positions, wl.intensities, order)
+    O2, P2, n2, _ = oracle.sweep_strict(wl.object0, wl.probe0, wl.positions, wl.intensities, order, mask=ones)
+    np.testing.assert_array_equal(O1, O2)
+    np.testing.assert_array_equal(P1, P2)
+    O3, P3, n3, _ = oracle.sweep_strict(wl.object0, wl.probe0, wl.positions, wl.intensities, order, mask=~ones)
+    np.testing.assert_allclose(O3, wl.object0, atol=1e-12)
+    np.testing.assert_allclose(P3, wl.probe0, atol=1e-12 * np.abs(wl.probe0).max())
+    assert n3 == 0.0
