@@ -116,6 +116,36 @@ def run_gpu(cfg_id, steps, warmup, form, positions=None):
                 ingest_s=ingest_s, err=float(err), kernels=kern)
 
 
+def run_forms(wl, steps, strict_steps=1):
+    """Updates/s of the other launch forms on the same workload: the sweep
+    graph, the persistent kernel, and strict ePIE (every position its own
+    batch: one group of three launches per position)."""
+    import torch
+
+    from paper_2308_10674_amd import Engine
+
+    out = {}
+    inten = torch.from_numpy(wl.intensities).cuda()
+    pos = torch.from_numpy(wl.positions).cuda()
+    for name, form, mode, k in (("graph", "graph", "coloured", steps), ("persistent", "persistent", "coloured", steps),
+                                ("per_position", "batch", "strict", strict_steps)):
+        eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode=mode, seed=wl.seed, form=form)
+        eng.add_positions(pos, inten)
+        eng.sweep(1)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        eng.sweep(k)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        out[name] = {"value": round(wl.count * k / (ms / 1e3), 1), "ms_per_step": round(ms / k, 3), "steps": k,
+                     "mode": mode}
+        eng.close()
+    out["unit"] = "position updates/s"
+    return out
+
+
 def roofline_of(r):
     """Roofline entry of the dominant kernel (largest summed event time)."""
     n = r["wl"].n
@@ -210,11 +240,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="batch", choices=["batch", "persistent"],
-                    help="batch: three launches per batch; persistent: one cooperative kernel per sweep")
+    ap.add_argument("--form", default="batch", choices=["batch", "persistent", "graph"],
+                    help="batch: three launches per batch; persistent: one cooperative kernel per sweep; "
+                         "graph: one HIP graph replay per sweep")
+    ap.add_argument("--no-forms", action="store_true", help="skip timing the other launch forms")
     ap.add_argument("--no-256", action="store_true", help="skip the 256 px workload")
     ap.add_argument("--steps-256", type=int, default=3)
-    ap.add_argument("--multi", action="store_true", help="also time 16 independent scans advanced together")
+    ap.add_argument("--no-multi", action="store_true", help="skip the 16 independent scans advanced together")
     ap.add_argument("--steps-multi", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -265,7 +297,14 @@ def main():
             "note": "whole sweep: 20 N^2 algorithmic bytes per position update over the timed wall time",
         },
         "error_after": r["err"],
+        "ingest": {
+            "GB_per_s": round(wl.count * wl.n * wl.n * 4 / r["ingest_s"] / 1e9, 2),
+            "note": "add_positions of device-resident float32 patterns (sqrt, schedule extension, "
+                    "first-time buffer allocation included)",
+        },
     }
+    if not args.no_forms:
+        out["forms"] = run_forms(wl, args.steps)
     if not args.no_256:
         r2 = run_gpu(2, args.steps_256, 1, args.form)
         out["n256"] = {
@@ -276,7 +315,7 @@ def main():
             "batches_per_sweep": r2["batches"], "mean_batch": round(r2["mean_batch"], 2),
             "roofline": roofline_of(r2),
         }
-    if args.multi:
+    if not args.no_multi:
         out["multi16"] = run_multi(args.steps_multi, 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds)

@@ -210,20 +210,28 @@ int ptyc_set_probe(ptyc_ctx* ctx, const void* in, int mem_kind);
 
 /* Launch form of a sweep: PTYC_FORM_BATCH (the default) launches three
  * kernels per batch; PTYC_FORM_PERSISTENT runs each sweep as one cooperative
- * kernel whose stages are separated by grid-wide barriers.  Both produce the
- * same bytes.  PTYC_FORM_DEFAULT selects PTYC_FORM_BATCH.  Errors:
- * PTYC_ERR_ARG for an unknown form or a persistent grid the device cannot
- * hold. */
+ * kernel whose stages are separated by grid-wide barriers; PTYC_FORM_GRAPH
+ * replays one instantiated HIP graph per sweep (the batch form's kernels as
+ * a chain of nodes that read their batch extents from device memory; built
+ * on the first sweep and again whenever the batch count grows, the largest
+ * batch grows or a buffer moves, e.g. after positions are added; each
+ * replay is preceded by two device-to-device copies of the sweep's order and
+ * offsets).  All forms produce the same bytes.  PTYC_FORM_DEFAULT selects
+ * PTYC_FORM_BATCH.  Errors: PTYC_ERR_ARG for an unknown form or a
+ * persistent grid the device cannot hold. */
 #define PTYC_FORM_DEFAULT 0
 #define PTYC_FORM_BATCH 1
 #define PTYC_FORM_PERSISTENT 2
+#define PTYC_FORM_GRAPH 3
 int ptyc_set_form(ptyc_ctx* ctx, int form);
 /* The current launch form (-1 for a NULL context). */
 int ptyc_get_form(const ptyc_ctx* ctx);
 
-/* Per-kernel timing.  While enabled, every sweep records HIP events on the
- * context's stream around each kernel launch (this adds a little host
- * work per launch); ptyc_profile_read synchronises the stream and returns,
+/* Per-kernel timing.  While enabled, every batch-form kernel is launched
+ * with a start and an end event bound to its own dispatch, so the interval
+ * is the kernel's execution (as a kernel trace reports it); the persistent
+ * sweep kernel is bracketed by events on the stream.  This adds a little
+ * host work per launch.  ptyc_profile_read synchronises the stream and returns,
  * for one kernel kind, the summed event time in milliseconds, the number of
  * launches and the number of position updates those launches processed.
  * ptyc_profile(ctx, enable) resets the totals.  Errors: PTYC_ERR_ARG for an
@@ -232,7 +240,8 @@ int ptyc_get_form(const ptyc_ctx* ctx);
 #define PTYC_KERNEL_COLS 1        /* column FFTs, modulus replacement, inverse column FFTs */
 #define PTYC_KERNEL_ROWS_INV 2    /* inverse row FFTs, object step, batch probe step */
 #define PTYC_KERNEL_SWEEP 3       /* the persistent sweep kernel */
-#define PTYC_KERNEL_KINDS 4
+#define PTYC_KERNEL_GRAPH 4       /* one replay of the sweep graph (graph form) */
+#define PTYC_KERNEL_KINDS 5
 int ptyc_profile(ptyc_ctx* ctx, int enable);
 int ptyc_profile_read(ptyc_ctx* ctx, int kind, double* total_ms, int64_t* launches,
                       int64_t* positions);

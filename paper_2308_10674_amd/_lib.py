@@ -20,11 +20,13 @@ PTYC_MODE_COLOURED = 1
 PTYC_FORM_DEFAULT = 0
 PTYC_FORM_BATCH = 1
 PTYC_FORM_PERSISTENT = 2
+PTYC_FORM_GRAPH = 3
 PTYC_KERNEL_ROWS_FWD = 0
 PTYC_KERNEL_COLS = 1
 PTYC_KERNEL_ROWS_INV = 2
 PTYC_KERNEL_SWEEP = 3
-KERNEL_NAMES = {0: "k_rows_fwd", 1: "k_cols", 2: "k_rows_inv", 3: "k_sweep"}
+PTYC_KERNEL_GRAPH = 4
+KERNEL_NAMES = {0: "k_rows_fwd", 1: "k_cols", 2: "k_rows_inv", 3: "k_sweep", 4: "sweep_graph"}
 PTYC_I_IS_SQRT = 1
 PTYC_I_CENTERED = 2
 

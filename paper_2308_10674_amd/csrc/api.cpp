@@ -42,7 +42,8 @@ struct ptyc_ctx {
     int64_t cap = 0, n_loaded = 0;
     DevBuf scratch, dprobe, winmax;  // per batch slot, capacity slots
     int64_t slots = 0;
-    DevBuf pmax_part;
+    DevBuf pmax_part;                // two halves of max_probe_blocks floats (see pmax_cur)
+    int pmax_cur = 0;                // the half holding the current probe's partial maxima
     DevBuf order;                    // int64 [order_cap]
     DevBuf offs;                     // int64 batch offsets of the persistent form
     DevBuf err_part, err_dev;
@@ -63,6 +64,14 @@ struct ptyc_ctx {
     bool upload_pending = false;
 
     size_t dev_bytes = 0, dev_limit = 0;
+
+    // launch form "graph": one instantiated sweep graph, rebuilt when the
+    // batch count, the largest batch or a buffer address changes; each sweep
+    // copies its order and offsets into gorder / goffs first
+    hipGraphExec_t gexec = nullptr;
+    BatchArgs gkey{};
+    int64_t g_nb = -1, g_maxb = -1;
+    DevBuf gorder, goffs;
 
     // optional per-kernel timing with events on the context's stream
     bool prof = false;
@@ -189,6 +198,8 @@ int max_row_blocks(const ptyc_ctx* c) { return std::max(c->sb.row_blocks, c->sp.
 int max_col_blocks(const ptyc_ctx* c) { return std::max(c->sb.col_blocks, c->sp.col_blocks); }
 int max_probe_blocks(const ptyc_ctx* c) { return std::max(c->sb.probe_blocks, c->sp.probe_blocks); }
 
+float* pmax_half(const ptyc_ctx* c, int k) { return (float*)c->pmax_part.p + (size_t)k * max_probe_blocks(c); }
+
 BatchArgs base_args(ptyc_ctx* c) {
     BatchArgs a{};
     a.obj = (cf*)c->obj.p;
@@ -202,7 +213,8 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.scratch = (cf*)c->scratch.p;
     a.dprobe = (cf*)c->dprobe.p;
     a.winmax = (float*)c->winmax.p;
-    a.pmax_part = (float*)c->pmax_part.p;
+    a.pmax_in = pmax_half(c, c->pmax_cur);
+    a.pmax_out = pmax_half(c, c->pmax_cur ^ 1);
     a.npmax = shape_of(c).probe_blocks;
     a.row_blocks = shape_of(c).row_blocks;
     a.err_part = (double*)c->err_part.p;
@@ -250,6 +262,7 @@ int refresh_probe_max(ptyc_ctx* c) {
     BatchArgs a = base_args(c);
     a.bsize = 0;
     HIPCHK(c, launch_probe_reduce(c->cfg.n, a, c->form, c->stream));
+    c->pmax_cur ^= 1;
     return PTYC_OK;
 }
 
@@ -343,7 +356,7 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     if ((rc = ensure(c, c->obj, obj_bytes)) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->probe, pr_bytes)) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->tw, n * sizeof(cf))) != PTYC_OK) return bail(rc);
-    if ((rc = ensure(c, c->pmax_part, max_probe_blocks(c) * sizeof(float))) != PTYC_OK) return bail(rc);
+    if ((rc = ensure(c, c->pmax_part, 2 * (size_t)max_probe_blocks(c) * sizeof(float))) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->bad, sizeof(int))) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->sync, 2 * sizeof(unsigned))) != PTYC_OK) return bail(rc);
     if ((e = hipMemsetAsync(c->sync.p, 0, 2 * sizeof(unsigned), c->stream)) != hipSuccess) {
@@ -374,7 +387,9 @@ void ptyc_destroy(ptyc_ctx* c) {
     if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
                       &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
-                      &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging};
+                      &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging,
+                      &c->gorder, &c->goffs};
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -400,7 +415,8 @@ int ptyc_set_form(ptyc_ctx* c, int form) {
     int rc = usable(c);
     if (rc) return rc;
     if (form == 0) form = kFormBatch;
-    if (form != kFormBatch && form != kFormPersistent) return fail(c, PTYC_ERR_ARG, "unknown launch form");
+    if (form != kFormBatch && form != kFormPersistent && form != kFormGraph)
+        return fail(c, PTYC_ERR_ARG, "unknown launch form");
     if (form == kFormPersistent && c->capacity <= 0)
         return fail(c, PTYC_ERR_ARG, "the persistent form cannot be launched on this device");
     c->form = form;
@@ -672,6 +688,7 @@ int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
     BatchArgs a = base_args(c);
     a.bsize = 0;
     HIPCHK(c, launch_probe_reduce(c->cfg.n, a, form, c->stream));
+    c->pmax_cur ^= 1;
     return PTYC_OK;
 }
 
@@ -682,6 +699,62 @@ int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, bool batch_layout) {
     const int64_t* ord = (const int64_t*)c->order.p + (size_t)s * p.olen;
     HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, p.olen * gc, ord, p.olen, (const double*)c->sum_i.p,
                                 (double*)c->err_dev.p + s, c->stream));
+    return PTYC_OK;
+}
+
+// do two graph keys name the same buffers and constants?
+bool same_key(const BatchArgs& x, const BatchArgs& y) {
+    return x.obj == y.obj && x.h == y.h && x.w == y.w && x.probe == y.probe && x.tw == y.tw &&
+           x.sqrt_i == y.sqrt_i && x.pos == y.pos && x.order == y.order && x.scratch == y.scratch &&
+           x.dprobe == y.dprobe && x.winmax == y.winmax && x.row_blocks == y.row_blocks &&
+           x.pmax_in == y.pmax_in && x.pmax_out == y.pmax_out && x.npmax == y.npmax && x.err_part == y.err_part &&
+           x.alpha == y.alpha && x.beta == y.beta && x.mask == y.mask && x.boffs == y.boffs;
+}
+
+// sweep s of a plan in the graph form: (re)build the graph if needed, copy
+// the sweep's order and offsets into the graph's fixed buffers, replay
+int graph_sweep(ptyc_ctx* c, const Plan& p, int s) {
+    int rc;
+    if ((rc = ensure(c, c->gorder, (size_t)p.olen * sizeof(int64_t))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->goffs, (size_t)(p.nb + 1) * sizeof(int64_t))) != PTYC_OK) return rc;
+    // the graph's first node reads the maxima from half 0
+    if (c->pmax_cur != 0 && (rc = refresh_probe_max(c)) != PTYC_OK) return rc;
+    BatchArgs a = base_args(c);
+    a.order = (const int64_t*)c->gorder.p;
+    a.boffs = (const int64_t*)c->goffs.p;
+    if (!c->gexec || c->g_nb != p.nb || c->g_maxb < p.max_b || !same_key(a, c->gkey)) {
+        if (c->gexec) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            HIPCHK(c, hipGraphExecDestroy(c->gexec));
+            c->gexec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(c, build_sweep_graph(c->cfg.n, a, (int)p.nb, (int)p.max_b, &g));
+        hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->gexec = nullptr;
+            return hip_fail(c, e, "hipGraphInstantiate");
+        }
+        c->gkey = a;
+        c->g_nb = p.nb;
+        c->g_maxb = p.max_b;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->gorder.p, (const int64_t*)c->order.p + (size_t)s * p.olen,
+                             (size_t)p.olen * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->goffs.p, (const int64_t*)c->offs.p + (size_t)s * (p.nb + 1),
+                             (size_t)(p.nb + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+    size_t e0 = 0;
+    if (c->prof) {
+        if ((rc = take_events(c, 2, &e0)) != PTYC_OK) return rc;
+        HIPCHK(c, hipEventRecord(c->ev_pool[e0], c->stream));
+    }
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    c->pmax_cur = (int)(p.nb & 1);
+    if (c->prof) {
+        HIPCHK(c, hipEventRecord(c->ev_pool[e0 + 1], c->stream));
+        c->marks.push_back({PTYC_KERNEL_GRAPH, e0, e0 + 1, p.olen});
+    }
     return PTYC_OK;
 }
 
@@ -721,24 +794,33 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                 HIPCHK(c, hipEventRecord(c->ev_pool[e0], c->stream));
             }
             HIPCHK(c, launch_sweep(c->cfg.n, a, ctl, (int)p.max_b, c->stream));
+            // the kernel swaps the maxima halves after every non-empty batch
+            const auto& f = p.offs[(size_t)s];
+            for (size_t b = 0; b + 1 < f.size(); ++b) c->pmax_cur ^= (f[b + 1] > f[b]) ? 1 : 0;
             if (c->prof) {
                 HIPCHK(c, hipEventRecord(c->ev_pool[e0 + 1], c->stream));
                 c->marks.push_back({PTYC_KERNEL_SWEEP, e0, e0 + 1, olen});
             }
+        } else if (c->form == kFormGraph) {
+            if ((rc = graph_sweep(c, p, s)) != PTYC_OK) return rc;
         } else {
             const auto& f = p.offs[(size_t)s];
             for (size_t b = 0; b + 1 < f.size(); ++b) {
                 a.off = f[b];
                 a.bsize = (int)(f[b + 1] - f[b]);
                 if (a.bsize == 0) continue;
+                a.pmax_in = pmax_half(c, c->pmax_cur);
+                a.pmax_out = pmax_half(c, c->pmax_cur ^ 1);
+                c->pmax_cur ^= 1;
                 if (c->prof) {
                     size_t e0 = 0;
-                    if ((rc = take_events(c, 4, &e0)) != PTYC_OK) return rc;
-                    hipEvent_t ev[4] = {c->ev_pool[e0], c->ev_pool[e0 + 1], c->ev_pool[e0 + 2], c->ev_pool[e0 + 3]};
+                    if ((rc = take_events(c, 6, &e0)) != PTYC_OK) return rc;
+                    hipEvent_t ev[6];
+                    for (int k = 0; k < 6; ++k) ev[k] = c->ev_pool[e0 + k];
                     HIPCHK(c, launch_batch(c->cfg.n, a, c->stream, ev));
                     c->marks.push_back({PTYC_KERNEL_ROWS_FWD, e0, e0 + 1, a.bsize});
-                    c->marks.push_back({PTYC_KERNEL_COLS, e0 + 1, e0 + 2, a.bsize});
-                    c->marks.push_back({PTYC_KERNEL_ROWS_INV, e0 + 2, e0 + 3, a.bsize});
+                    c->marks.push_back({PTYC_KERNEL_COLS, e0 + 2, e0 + 3, a.bsize});
+                    c->marks.push_back({PTYC_KERNEL_ROWS_INV, e0 + 4, e0 + 5, a.bsize});
                 } else {
                     HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
                 }
@@ -776,19 +858,24 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
         if (plans[(size_t)i].olen > 0 && (rc = stage_plan(ctxs[i], plans[(size_t)i], n_sweeps, kFormBatch)) != PTYC_OK)
             return rc;
     // one step advances every unfinished context by one batch; per pattern
-    // size, each step is three launches covering all of that size's batches
+    // size, each step is three launches covering all of that size's batches.
+    // (The sizes share nothing, but running them on streams of their own was
+    // measured slower: each kernel boundary's cache maintenance then lands
+    // in the middle of the other streams' kernels.)
     int64_t steps = 0;
     for (int i = 0; i < n_ctx; ++i) steps = std::max(steps, (int64_t)n_sweeps * plans[(size_t)i].nb);
-    const int sizes[] = {16, 32, 64, 128, 256};
+    constexpr int kSizes[] = {16, 32, 64, 128, 256};
     std::vector<BatchArgs> tab;
-    struct Launch { int n; size_t first; int count; };
-    std::vector<Launch> launches;                 // per (step, size) with any work
-    std::vector<std::vector<std::pair<int, int>>> ends((size_t)steps);  // (context, sweep) finishing at a step
-    std::vector<size_t> step_first((size_t)steps + 1, 0);               // launches of step k: [first[k], first[k+1])
+    struct Launch {
+        int n;
+        size_t first;
+        int count;
+        std::vector<std::pair<int, int>> ends;    // (context, sweep) whose sweep ends with this launch
+    };
+    std::vector<Launch> work;                     // in step order
     for (int64_t k = 0; k < steps; ++k) {
-        step_first[(size_t)k] = launches.size();
-        for (int n : sizes) {
-            Launch L{n, tab.size(), 0};
+        for (int n : kSizes) {
+            Launch L{n, tab.size(), 0, {}};
             for (int i = 0; i < n_ctx; ++i) {
                 ptyc_ctx* c = ctxs[i];
                 const Plan& p = plans[(size_t)i];
@@ -798,17 +885,17 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
                 BatchArgs a = base_args(c);
                 a.row_blocks = c->sb.row_blocks;
                 a.npmax = c->sb.probe_blocks;
+                c->pmax_cur ^= 1;   // this entry's inverse stage writes the other half
                 a.order = (const int64_t*)c->order.p + (size_t)s * p.olen;
                 a.off = p.offs[(size_t)s][(size_t)b];
                 a.bsize = (int)(p.offs[(size_t)s][(size_t)b + 1] - a.off);
                 tab.push_back(a);
                 ++L.count;
-                if (b == p.nb - 1) ends[(size_t)k].push_back({i, s});
+                if (b == p.nb - 1) L.ends.push_back({i, s});
             }
-            if (L.count) launches.push_back(L);
+            if (L.count) work.push_back(std::move(L));
         }
     }
-    step_first[(size_t)steps] = launches.size();
     ptyc_ctx* c0 = ctxs[0];
     // the descriptor table may still be read by an earlier call's kernels
     HIPCHK(c0, hipStreamSynchronize(c0->stream));
@@ -818,14 +905,11 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
                                   c0->stream));
         HIPCHK(c0, hipStreamSynchronize(c0->stream));
     }
-    for (int64_t k = 0; k < steps; ++k) {
-        for (size_t li = step_first[(size_t)k]; li < step_first[(size_t)k + 1]; ++li) {
-            const Launch& L = launches[li];
-            HIPCHK(c0, launch_batch_multi(L.n, (const BatchArgs*)c0->multi.p + L.first, tab.data() + L.first, L.count,
-                                          c0->stream));
-        }
+    for (const Launch& L : work) {
+        HIPCHK(c0, launch_batch_multi(L.n, (const BatchArgs*)c0->multi.p + L.first, tab.data() + L.first, L.count,
+                                      c0->stream));
         if (err_out)
-            for (auto [i, s] : ends[(size_t)k])
+            for (auto [i, s] : L.ends)
                 if ((rc = launch_sweep_error(ctxs[i], plans[(size_t)i], s, true)) != PTYC_OK) return rc;
     }
     for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps_done += n_sweeps;

@@ -23,7 +23,12 @@ struct BatchArgs {
     cf* dprobe;               // [slots][n][n] per-position probe increments
     float* winmax;            // [slots][row_blocks] partial max |S_j O|^2
     int row_blocks;           // forward row items per position (winmax stride)
-    float* pmax_part;         // [npmax] partial max |P|^2 of the current probe
+    // partial maxima of |P|^2 per probe row block, double-buffered: the
+    // inverse row stage reads those of P_b from pmax_in and writes those of
+    // P_{b+1} to pmax_out, so no workgroup can read a partial that another
+    // workgroup of the same launch has already replaced
+    const float* pmax_in;     // [npmax]
+    float* pmax_out;          // [npmax]
     int npmax;                // number of probe row blocks
     double* err_part;         // [order_len][column blocks] error partial sums
     float alpha, beta;
@@ -31,6 +36,8 @@ struct BatchArgs {
     cf* gprobe;               // amplitude-loss gradient w.r.t. the probe (accumulated)
     float gscale;             // upstream scale of the gradient
     const unsigned char* mask;  // [n][n] 1 = measured detector pixel; nullptr: all measured
+    const int64_t* boffs;     // if set: off and bsize are read from boffs[batch], boffs[batch + 1]
+    int batch;
 };
 
 // How raw detector frames become stored amplitudes.
@@ -48,7 +55,7 @@ struct IngestSpec {
 enum : int { kModeEpie = 0, kModeGrad = 1, kModeLoss = 2 };
 
 // Launch forms of a sweep.
-enum : int { kFormBatch = 1, kFormPersistent = 2 };
+enum : int { kFormBatch = 1, kFormPersistent = 2, kFormGraph = 3 };
 
 // Work split per pattern size and launch form.
 struct Shape {
@@ -69,10 +76,10 @@ struct SweepCtl {
 bool supported_n(int n);
 Shape shape_for(int n, int form);
 
-// ev: NULL, or four events recorded before the first kernel and after each
-// of the three kernels of the batch
+// ev: NULL, or six events: the start and end of each of the three kernels
+// of the batch, taken from the kernel dispatches themselves
 hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
-// the partial maxima of |P|^2 of the current probe (no update)
+// the partial maxima of |P|^2 of the current probe (no update), into a.pmax_out
 hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s);
 // one batch of each of `count` independent reconstructions with pattern
 // size n (three launches): dev_tab on the device, host_tab the same
@@ -81,7 +88,18 @@ constexpr int kMultiMax = 64;
 hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* host_tab, int count,
                               hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel
+// The persistent sweep swaps a.pmax_in and a.pmax_out after every non-empty
+// batch.
 hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s);
+// One sweep of nb batches as a graph of 3 nb kernel nodes in a chain.  The
+// nodes read their batch's offset and size from a.boffs (a.boffs[b] ..
+// a.boffs[b + 1] in a.order) when they run, and their grids cover max_b
+// slots, so the instantiated graph serves every sweep with nb batches of at
+// most max_b positions over the same buffers.  Batch 0 reads the probe
+// maxima from a.pmax_in; the halves alternate from node to node (every
+// node, empty or not, writes the other half), so after the graph the
+// current maxima are in a.pmax_in when nb is even, else in a.pmax_out.
+hipError_t build_sweep_graph(int n, const BatchArgs& a, int nb, int max_b, hipGraph_t* out);
 // amplitude loss over one batch of disjoint windows; grad: also accumulate
 // dL/dO into gobj and dL/dP into gprobe
 hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s);

@@ -19,6 +19,7 @@
 // Launch forms: per batch, three kernel launches (k_rows_fwd, k_cols,
 // k_rows_inv); or one cooperative kernel per sweep (k_sweep) that runs the
 // same stage functions separated by grid-wide barriers.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -278,7 +279,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         float ostep = 0.f;
         if (MODE == kModeEpie) {
             float pm = 0.f;
-            for (int i = threadIdx.x; i < a.npmax; i += g::NT) pm = fmaxf(pm, a.pmax_part[i]);
+            for (int i = threadIdx.x; i < a.npmax; i += g::NT) pm = fmaxf(pm, a.pmax_in[i]);
             pm = block_max<g::NT>(pm, red);
             ostep = a.alpha / pm;
         }
@@ -351,7 +352,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             a.probe[own] = pn;
         }
         const float m = block_max<g::NT>(norm2(pn), red);
-        if (threadIdx.x == 0) a.pmax_part[rb] = m;
+        if (threadIdx.x == 0) a.pmax_out[rb] = m;
     } else if (a.bsize > 0 && owner) {
         a.gprobe[own] = p_own + acc;
     }
@@ -362,13 +363,27 @@ template <int N> constexpr int kRowNT = RowG<N, Tile<N>::RB>::NT;
 template <int N> constexpr int kColNT = ColG<N, Tile<N>::CB>::NT;
 template <int N> constexpr int kSweepNT = RowG<N, PTile<N>::B>::NT;
 
+// A graph node does not know its batch's extent when it is built: it reads
+// the offset and size from the device offsets array (uniform loads).
+__device__ __forceinline__ BatchArgs resolved(const BatchArgs& a) {
+    BatchArgs r = a;
+    if (a.boffs) {
+        r.off = a.boffs[a.batch];
+        r.bsize = (int)(a.boffs[a.batch + 1] - r.off);
+    }
+    return r;
+}
+
 template <int N>
 __global__ __launch_bounds__(kRowNT<N>) void k_rows_fwd(BatchArgs a) {
     constexpr int RB = Tile<N>::RB;
     using g = RowG<N, RB>;
     __shared__ cf lds[RB * Lds<N>::LINE];
     __shared__ float red[g::NT / kWave];
-    stage_rows_fwd<N, RB>(a, blockIdx.x / g::G, blockIdx.x % g::G, lds, red);
+    const BatchArgs b = resolved(a);
+    const int slot = blockIdx.x / g::G;
+    if (slot >= b.bsize) return;   // a grid sized for a larger batch (whole workgroup)
+    stage_rows_fwd<N, RB>(b, slot, blockIdx.x % g::G, lds, red);
 }
 
 template <int N>
@@ -377,7 +392,10 @@ __global__ __launch_bounds__(kColNT<N>) void k_cols(BatchArgs a) {
     using g = ColG<N, CB>;
     __shared__ cf lds[CB * Lds<N>::LINE];
     __shared__ double red[g::NT / kWave];
-    stage_cols<N, CB>(a, blockIdx.x / g::GC, blockIdx.x % g::GC, lds, red);
+    const BatchArgs b = resolved(a);
+    const int slot = blockIdx.x / g::GC;
+    if (slot >= b.bsize) return;
+    stage_cols<N, CB>(b, slot, blockIdx.x % g::GC, lds, red);
 }
 
 template <int N, int R = ITile<N>::R, int S = ITile<N>::S>
@@ -386,7 +404,7 @@ __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
     __shared__ cf dl[g::S * g::R * N];
     __shared__ float red[g::NT / kWave];
-    stage_rows_inv<N, g::R, g::S>(a, blockIdx.x, lds, dl, red);
+    stage_rows_inv<N, g::R, g::S>(resolved(a), blockIdx.x, lds, dl, red);
 }
 
 // Several reconstructions at once: workgroup b belongs to descriptor i with
@@ -544,6 +562,10 @@ __global__ __launch_bounds__(kSweepNT<N>) void k_sweep(BatchArgs a, SweepCtl c) 
         for (int it = blockIdx.x; it < ig::GI; it += gridDim.x)
             stage_rows_inv<N, ig::R, ig::S>(a, it, lds, dl, redf);
         if (!grid_barrier(c, ++epoch, &ok_sh)) return;
+        // the maxima just written are those of the next batch's probe
+        float* const next_in = a.pmax_out;
+        a.pmax_out = const_cast<float*>(a.pmax_in);
+        a.pmax_in = next_in;
     }
 }
 
@@ -620,16 +642,66 @@ template <int N>
 hipError_t batch_n(const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
     using rg = RowG<N, Tile<N>::RB>;
     using cg = ColG<N, Tile<N>::CB>;
-    if (ev) (void)hipEventRecord(ev[0], s);
+    if (ev) {
+        // ev[2k], ev[2k+1]: the start and end of kernel k, taken from its
+        // own dispatch (not from markers between launches)
+        if (a.bsize > 0) {
+            hipExtLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, ev[0], ev[1], 0, a);
+            hipExtLaunchKernelGGL(k_cols<N>, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, ev[2], ev[3], 0, a);
+        }
+        hipExtLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, ev[4], ev[5], 0, a);
+        return hipGetLastError();
+    }
     if (a.bsize > 0) {
         hipLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
-        if (ev) (void)hipEventRecord(ev[1], s);
         hipLaunchKernelGGL(k_cols<N>, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
-        if (ev) (void)hipEventRecord(ev[2], s);
     }
     hipLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
+}
+
+template <int N>
+hipError_t graph_n(const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
+    using rg = RowG<N, Tile<N>::RB>;
+    using cg = ColG<N, Tile<N>::CB>;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t prev = nullptr;
+    auto add = [&](const void* fn, int grid, int nt, BatchArgs* args) {
+        void* params[] = {args};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(fn);
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(nt);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = params;
+        kp.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        hipError_t r = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (r == hipSuccess) prev = node;
+        return r;
+    };
+    for (int b = 0; b < nb && e == hipSuccess; ++b) {
+        BatchArgs ab = a;
+        ab.batch = b;
+        if (b & 1) {   // every node's inverse stage writes the other half (an empty batch refreshes it)
+            ab.pmax_in = a.pmax_out;
+            ab.pmax_out = const_cast<float*>(a.pmax_in);
+        }
+        ab.off = 0;
+        ab.bsize = 0;
+        e = add(reinterpret_cast<const void*>(&k_rows_fwd<N>), rg::G * max_b, rg::NT, &ab);
+        if (e == hipSuccess) e = add(reinterpret_cast<const void*>(&k_cols<N>), cg::GC * max_b, cg::NT, &ab);
+        if (e == hipSuccess)
+            e = add(reinterpret_cast<const void*>(&k_rows_inv<N>), InvG<N>::GI, InvG<N>::NT, &ab);
+    }
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    *out = g;
+    return hipSuccess;
 }
 
 template <int N>
@@ -766,6 +838,12 @@ int persistent_capacity(int n) {
 
 hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s) {
     PTYC_DISPATCH(n, sweep_n<N>(a, c, max_batch, s));
+    return hipErrorInvalidValue;
+}
+
+hipError_t build_sweep_graph(int n, const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
+    if (nb < 0 || max_b <= 0 || !a.boffs || !out) return hipErrorInvalidValue;
+    PTYC_DISPATCH(n, graph_n<N>(a, nb, max_b, out));
     return hipErrorInvalidValue;
 }
 

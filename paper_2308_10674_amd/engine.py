@@ -223,12 +223,13 @@ class Engine:
     @property
     def form(self) -> str:
         f = int(L.lib().ptyc_get_form(self._ctx))
-        return {L.PTYC_FORM_BATCH: "batch", L.PTYC_FORM_PERSISTENT: "persistent"}.get(f, str(f))
+        return {L.PTYC_FORM_BATCH: "batch", L.PTYC_FORM_PERSISTENT: "persistent",
+                L.PTYC_FORM_GRAPH: "graph"}.get(f, str(f))
 
     @form.setter
     def form(self, name):
         code = {"default": L.PTYC_FORM_DEFAULT, "batch": L.PTYC_FORM_BATCH,
-                "persistent": L.PTYC_FORM_PERSISTENT}[name]
+                "persistent": L.PTYC_FORM_PERSISTENT, "graph": L.PTYC_FORM_GRAPH}[name]
         _check(L.lib().ptyc_set_form(self._ctx, code), self._ctx)
 
     @property

@@ -43,6 +43,19 @@ def test_library_exports_every_declared_symbol():
     assert lib.ptyc_version() >= 100
 
 
+def test_binding_constants_match_header():
+    """Every numeric #define of the header that the binding names has the
+    header's value, and every kernel kind has a name."""
+    text = open(HEADER).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define\s+(PTYC_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text)}
+    named = {k: getattr(L, k) for k in dir(L) if k.startswith("PTYC_") and isinstance(getattr(L, k), int)}
+    assert named, "binding names no constants"
+    for k, v in named.items():
+        assert k in defs, k
+        assert defs[k] == v, (k, defs[k], v)
+    assert sorted(L.KERNEL_NAMES) == list(range(defs["PTYC_KERNEL_KINDS"]))
+
+
 def _cfg(**kw):
     base = dict(n=32, h=64, w=64, alpha=1.0, beta=1.0, mode=0, max_batch=0, seed=1, flags=0, reserved=0)
     base.update(kw)

@@ -78,10 +78,10 @@ def test_config0_every_position():
         O, P, _, _ = oracle.sweep_strict(O, P, wl.positions, wl.intensities, order)
 
 
-@pytest.mark.parametrize("form", ["persistent", "batch"])
+@pytest.mark.parametrize("form", ["persistent", "batch", "graph"])
 def test_coloured_128_every_batch(form):
     """128 px, first 600 raster positions: every batch of the library's
-    first two sweeps re-synced, in both launch forms."""
+    first two sweeps re-synced, in every launch form."""
     wl = sim.make_config(1, n_positions=600)
     eng = engine_for(wl, form=form)
     assert eng.form == form
@@ -93,10 +93,10 @@ def test_coloured_128_every_batch(form):
         eng.sweep(1, order=order, batch_offsets=off)     # advance the sweep counter
 
 
-@pytest.mark.parametrize("form", ["persistent", "batch"])
+@pytest.mark.parametrize("form", ["persistent", "batch", "graph"])
 def test_coloured_256_every_batch(form):
     """256 px on the 2048^2 object (every 30th spiral position): every batch
-    of the first sweep re-synced, in both launch forms."""
+    of the first sweep re-synced, in every launch form."""
     c = sim.CONFIGS[2]
     pos = sim.fermat_positions(20000, 6.0, 256, 2048)[::30]
     wl = sim.make_workload(256, 2048, c["radius"], c["kappa"], pos, c["photons"], 1002, config=2)
@@ -248,16 +248,53 @@ def test_max_batch_cap_and_explicit_batches():
 
 @pytest.mark.parametrize("cfg,count,mode", [(1, 600, "coloured"), (0, 100, "strict"), (2, 400, "coloured")])
 def test_launch_forms_agree_bitwise(cfg, count, mode):
-    """The persistent sweep kernel and the per-batch launches perform the same
-    per-element arithmetic: identical object and probe bytes."""
+    """The persistent sweep kernel, the per-batch launches and the sweep
+    graph perform the same per-element arithmetic: identical object and
+    probe bytes."""
     wl = sim.make_config(cfg, n_positions=count)
-    a = engine_for(wl, mode=mode, form="persistent")
     b = engine_for(wl, mode=mode, form="batch")
-    ea = a.sweep(2, errors=True)
     eb = b.sweep(2, errors=True)
-    np.testing.assert_array_equal(a.get_object(), b.get_object())
-    np.testing.assert_array_equal(a.get_probe(), b.get_probe())
-    np.testing.assert_allclose(ea, eb, rtol=1e-12)
+    for form in ("persistent", "graph"):
+        a = engine_for(wl, mode=mode, form=form)
+        ea = a.sweep(2, errors=True)
+        np.testing.assert_array_equal(a.get_object(), b.get_object(), err_msg=form)
+        np.testing.assert_array_equal(a.get_probe(), b.get_probe(), err_msg=form)
+        np.testing.assert_allclose(ea, eb, rtol=1e-12, err_msg=form)
+        a.close()
+
+
+def test_graph_form_follows_growth_and_schedules():
+    """The sweep graph is rebuilt when positions are added (more batches,
+    larger batches, a grown order buffer) and serves explicit schedules of
+    other shapes; every step stays bit-identical to the per-batch form, and
+    the profiler records one interval per replay."""
+    wl = sim.make_config(1, n_positions=600)
+    g = engine_for(wl, count=0, form="graph")
+    b = engine_for(wl, count=0, form="batch")
+    g.profile(True)
+    for lo, hi, sweeps in ((0, 200, 2), (200, 400, 1), (400, 600, 3)):
+        for e in (g, b):
+            e.add_positions(wl.positions[lo:hi], wl.intensities[lo:hi])
+            e.sweep(sweeps)
+        np.testing.assert_array_equal(g.get_object(), b.get_object())
+        np.testing.assert_array_equal(g.get_probe(), b.get_probe())
+    prof = g.profile_read()
+    assert prof["sweep_graph"][1] == 6 and prof["sweep_graph"][2] == 2 * 200 + 400 + 3 * 600
+    # explicit schedules: fewer batches, then singletons
+    order, off = b.get_schedule()
+    for o, f in ((order[:90], None), (order, off)):
+        if f is None:
+            f = [0]
+            for j in range(len(o)):
+                if j and any(oracle.windows_overlap(wl.positions[o[j]], wl.positions[o[k]], wl.n)
+                             for k in range(f[-1], j)):
+                    f.append(j)
+            f.append(len(o))
+        eg = g.sweep(1, order=o, batch_offsets=f, errors=True)
+        eb = b.sweep(1, order=o, batch_offsets=f, errors=True)
+        np.testing.assert_array_equal(g.get_object(), b.get_object())
+        np.testing.assert_array_equal(g.get_probe(), b.get_probe())
+        np.testing.assert_allclose(eg, eb, rtol=1e-12)
 
 def test_default_schedule_matches_exported_and_is_deterministic():
     wl = sim.make_config(1, n_positions=400)
