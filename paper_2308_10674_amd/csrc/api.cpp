@@ -215,8 +215,6 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.winmax = (float*)c->winmax.p;
     a.pmax_in = pmax_half(c, c->pmax_cur);
     a.pmax_out = pmax_half(c, c->pmax_cur ^ 1);
-    a.npmax = shape_of(c).probe_blocks;
-    a.row_blocks = shape_of(c).row_blocks;
     a.err_part = (double*)c->err_part.p;
     a.alpha = c->cfg.alpha;
     a.beta = c->cfg.beta;
@@ -706,8 +704,8 @@ int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, bool batch_layout) {
 bool same_key(const BatchArgs& x, const BatchArgs& y) {
     return x.obj == y.obj && x.h == y.h && x.w == y.w && x.probe == y.probe && x.tw == y.tw &&
            x.sqrt_i == y.sqrt_i && x.pos == y.pos && x.order == y.order && x.scratch == y.scratch &&
-           x.dprobe == y.dprobe && x.winmax == y.winmax && x.row_blocks == y.row_blocks &&
-           x.pmax_in == y.pmax_in && x.pmax_out == y.pmax_out && x.npmax == y.npmax && x.err_part == y.err_part &&
+           x.dprobe == y.dprobe && x.winmax == y.winmax &&
+           x.pmax_in == y.pmax_in && x.pmax_out == y.pmax_out && x.err_part == y.err_part &&
            x.alpha == y.alpha && x.beta == y.beta && x.mask == y.mask && x.boffs == y.boffs;
 }
 
@@ -883,8 +881,6 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
                 const int s = (int)(k / p.nb);
                 const int64_t b = k % p.nb;
                 BatchArgs a = base_args(c);
-                a.row_blocks = c->sb.row_blocks;
-                a.npmax = c->sb.probe_blocks;
                 c->pmax_cur ^= 1;   // this entry's inverse stage writes the other half
                 a.order = (const int64_t*)c->order.p + (size_t)s * p.olen;
                 a.off = p.offs[(size_t)s][(size_t)b];
@@ -1045,7 +1041,6 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
     if ((rc = ensure(c, c->err_dev, sizeof(double))) != PTYC_OK) return rc;
     HIPCHK(c, hipMemcpyAsync(c->order.p, order.data(), obytes, hipMemcpyHostToDevice, c->stream));
     BatchArgs a = base_args(c);
-    a.row_blocks = c->sb.row_blocks;
     a.obj = (cf*)obj;
     a.probe = (cf*)probe;
     a.gobj = (cf*)grad_obj;

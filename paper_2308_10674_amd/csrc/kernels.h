@@ -21,15 +21,13 @@ struct BatchArgs {
     int bsize;                // positions in this batch
     cf* scratch;              // [slots][n][n] spectrum exchange between stages
     cf* dprobe;               // [slots][n][n] per-position probe increments
-    float* winmax;            // [slots][row_blocks] partial max |S_j O|^2
-    int row_blocks;           // forward row items per position (winmax stride)
+    float* winmax;            // [slots][Shape::row_blocks] partial max |S_j O|^2, one per forward-stage wave
     // partial maxima of |P|^2 per probe row block, double-buffered: the
     // inverse row stage reads those of P_b from pmax_in and writes those of
     // P_{b+1} to pmax_out, so no workgroup can read a partial that another
     // workgroup of the same launch has already replaced
-    const float* pmax_in;     // [npmax]
-    float* pmax_out;          // [npmax]
-    int npmax;                // number of probe row blocks
+    const float* pmax_in;     // [Shape::probe_blocks]
+    float* pmax_out;          // [Shape::probe_blocks]
     double* err_part;         // [order_len][column blocks] error partial sums
     float alpha, beta;
     cf* gobj;                 // amplitude-loss gradient w.r.t. the object (accumulated)
@@ -59,9 +57,9 @@ enum : int { kFormBatch = 1, kFormPersistent = 2, kFormGraph = 3 };
 
 // Work split per pattern size and launch form.
 struct Shape {
-    int row_blocks;   // row items per position (winmax entries per slot)
+    int row_blocks;   // winmax entries per slot (per-wave partials)
     int col_blocks;   // column items per position (error partials per position)
-    int probe_blocks; // probe items (pmax_part entries)
+    int probe_blocks; // pmax entries (per-wave partials)
 };
 
 // Controls of the persistent sweep kernel.

@@ -44,6 +44,15 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// max over aligned groups of G consecutive lanes (G a power of two, at most
+// a wave); every lane of a group gets the group's result
+template <int G>
+__device__ inline float group_max(float v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
 // block-wide max; every thread gets the result
 template <int NT>
 __device__ inline float block_max(float v, float* sh) {
@@ -104,12 +113,15 @@ template <> struct Tile<128> { static constexpr int RB = PTYC_RB128, CB = PTYC_C
 template <> struct Tile<256> { static constexpr int RB = PTYC_RB256, CB = PTYC_CB256; };
 
 // Inverse row stage: R rows for S slots at a time (S*R*N2 threads); for the
-// probe step thread i < R*N owns element i of the block's R rows.
+// probe step thread i < R*N owns element i of the block's R rows.  At 128 px
+// S = 40 holds the largest colour batches of a dense raster (36) in one
+// round; at 256 px the LDS allows at most 36 slots, which measured slower
+// than two rounds of 32.
 #ifndef PTYC_IR128
 #define PTYC_IR128 1
 #endif
 #ifndef PTYC_IS128
-#define PTYC_IS128 32
+#define PTYC_IS128 40
 #endif
 #ifndef PTYC_IR256
 #define PTYC_IR256 1
@@ -136,7 +148,7 @@ template <> struct PTile<256> { static constexpr int B = 16, R = 1, S = 16; };
 template <int N, int RB> struct RowG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
     static constexpr int G = N / RB, NT = RB * T;
-    static_assert(N % RB == 0 && NT % kWave == 0, "row tile");
+    static_assert(N % RB == 0 && NT % kWave == 0 && G * (NT / kWave) == N * N2 / kWave, "row tile");
 };
 template <int N, int CB> struct ColG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
@@ -147,12 +159,21 @@ template <int N, int R_ = ITile<N>::R, int S_ = ITile<N>::S> struct InvG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
     static constexpr int R = R_, S = S_;
     static constexpr int NT = S * R * T, GI = N / R;
-    static_assert(R * N <= NT && NT % kWave == 0 && N % R == 0, "inverse tile");
+    static_assert(R * N <= NT && NT % kWave == 0 && N % R == 0 && (R * N) % kWave == 0, "inverse tile");
 };
+
+// The maxima travel between stages as per-wave partials: the forward row
+// stage leaves kWinParts entries of max |S_j O|^2 per position (N / RB
+// workgroups of RB N2 / 64 waves, whatever RB), the inverse row stage
+// kProbeParts entries of max |P|^2 (N / R workgroups of R N / 64 owner
+// waves, whatever R); both counts are the same in every launch form.
+template <int N> constexpr int kWinParts = N * Fact<N>::N2 / kWave;
+template <int N> constexpr int kProbeParts = N * N / kWave;
 
 // ---------------------------------------------------------------- stage 1
 // psi = P * S_j O for rows rb*RB .. rb*RB+RB-1 of slot `slot`, 1D FFT of
-// each row, spectrum rows to scratch; partial max |S_j O|^2 to winmax.
+// each row, spectrum rows to scratch; partial max |S_j O|^2 to winmax, one
+// entry per wave (no workgroup barrier: a maximum is exact in any order).
 template <int N, int RB>
 __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds,
                                                float* red) {
@@ -181,8 +202,8 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
     for (int mm = 0; mm < g::N1 / g::N2; ++mm)
 #pragma unroll
         for (int k2 = 0; k2 < g::N2; ++k2) srow[(t + g::N2 * mm) + g::N1 * k2] = v[mm * g::N2 + k2];
-    m = block_max<g::NT>(m, red);
-    if (threadIdx.x == 0) a.winmax[slot * a.row_blocks + rb] = m;
+    m = wave_max(m);
+    if (threadIdx.x % kWave == 0) a.winmax[slot * kWinParts<N> + rb * (g::NT / kWave) + threadIdx.x / kWave] = m;
 }
 
 // ---------------------------------------------------------------- stage 2
@@ -278,9 +299,14 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = prow[g::N2 * n1 + t];
         float ostep = 0.f;
         if (MODE == kModeEpie) {
+            // every wave reduces all partial maxima itself (no barrier)
             float pm = 0.f;
-            for (int i = threadIdx.x; i < a.npmax; i += g::NT) pm = fmaxf(pm, a.pmax_in[i]);
-            pm = block_max<g::NT>(pm, red);
+#pragma unroll
+            for (int k = 0; k < (kProbeParts<N> + kWave - 1) / kWave; ++k) {
+                const int i = k * kWave + (int)(threadIdx.x % kWave);
+                if (i < kProbeParts<N>) pm = fmaxf(pm, a.pmax_in[i]);
+            }
+            pm = wave_max(pm);
             ostep = a.alpha / pm;
         }
         cf* z = lds + (sl * g::R + rl) * Lds<N>::LINE;
@@ -302,16 +328,27 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                         v[mm * g::N2 + k2] = srow[(t + g::N2 * mm) + g::N1 * k2];
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = orow[g::N2 * n1 + t];
-                if (MODE == kModeEpie) {
-                    om = 0.f;
-                    for (int i = 0; i < a.row_blocks; ++i) om = fmaxf(om, a.winmax[slot * a.row_blocks + i]);
-                }
             } else {
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     v[n1] = cf{0.f, 0.f};
                     o[n1] = cf{0.f, 0.f};
                 }
+            }
+            if (MODE == kModeEpie) {
+                // max |S_j O|^2 from the forward stage's per-wave partials,
+                // reduced by the slot's own threads (an idle slot reads
+                // slot 0's, which exists, and discards the result)
+                constexpr int GT = g::T * g::R;
+                const int ws = act ? slot : 0;
+                float wm = 0.f;
+#pragma unroll
+                for (int k = 0; k < (kWinParts<N> + GT - 1) / GT; ++k) {
+                    const int i = k * GT + (int)(threadIdx.x % GT);
+                    if (i < kWinParts<N>) wm = fmaxf(wm, a.winmax[ws * kWinParts<N> + i]);
+                }
+                wm = group_max<GT>(wm);
+                if (act) om = wm;
             }
             passBinv_to_lds<N, +1>(v, z, t, a.tw);
             __syncthreads();
@@ -340,8 +377,19 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             __syncthreads();
             // slot order: this group's slots ascending, after the earlier groups
             const int nact = min(g::S, a.bsize - g0);
-            if (owner)
-                for (int q = 0; q < nact; ++q) acc = acc + dl[(q * g::R + own_rl) * N + own_c];
+            if (owner) {
+                // the same sequential sum, with eight loads in flight at a time
+                const cf* col = dl + own_rl * N + own_c;
+                int q = 0;
+                for (; q + 8 <= nact; q += 8) {
+                    cf tq[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) tq[u] = col[(size_t)(q + u) * g::R * N];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc = acc + tq[u];
+                }
+                for (; q < nact; ++q) acc = acc + col[(size_t)q * g::R * N];
+            }
             __syncthreads();
         }
     }
@@ -351,8 +399,10 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             pn = p_own + (a.beta / (float)a.bsize) * acc;
             a.probe[own] = pn;
         }
-        const float m = block_max<g::NT>(norm2(pn), red);
-        if (threadIdx.x == 0) a.pmax_out[rb] = m;
+        // one partial per wave that owns probe elements (waves past R*N own none)
+        const float m = wave_max(norm2(pn));
+        if (threadIdx.x % kWave == 0 && threadIdx.x < g::R * N)
+            a.pmax_out[rb * (g::R * N / kWave) + threadIdx.x / kWave] = m;
     } else if (a.bsize > 0 && owner) {
         a.gprobe[own] = p_own + acc;
     }
@@ -631,11 +681,8 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
 // ---------------------------------------------------------------- host side
 template <int N>
 Shape shape_n(int form) {
-    if (form == kFormPersistent) {
-        constexpr int TB = PTile<N>::B;
-        return Shape{N / TB, N / TB, InvG<N, PTile<N>::R, PTile<N>::S>::GI};
-    }
-    return Shape{N / Tile<N>::RB, N / Tile<N>::CB, InvG<N>::GI};
+    if (form == kFormPersistent) return Shape{kWinParts<N>, N / PTile<N>::B, kProbeParts<N>};
+    return Shape{kWinParts<N>, N / Tile<N>::CB, kProbeParts<N>};
 }
 
 template <int N>
