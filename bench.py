@@ -209,6 +209,71 @@ def run_multi(steps, warmup, n_scans=16):
     }
 
 
+def run_adam_vs_epie(epochs, minibatch, lr, max_sweeps):
+    """Gradient reconstruction against ePIE on the 128 px raster workload
+    (3600 positions), both from the same start (flat object, Gaussian
+    probe): Adam on the amplitude loss over shuffled minibatches (the last
+    partial minibatch kept), and coloured ePIE sweeps.  Both are scored by
+    the same full-data Fourier error, L(O, P) / sum I, evaluated by the loss
+    kernel after every epoch or sweep; reported: Adam's final error and
+    time, and the sweeps and time ePIE needs to reach that error."""
+    import torch
+
+    import sim
+    from paper_2308_10674_amd import Engine, amplitude_loss
+
+    wl = sim.make_config(3)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(torch.from_numpy(wl.positions).cuda(), torch.from_numpy(wl.intensities).cuda())
+    total_i = float(wl.intensities.sum(dtype=np.float64))
+    full = np.arange(wl.count)
+
+    def ferr(o, p):
+        return eng.amp_loss(o, p, full) / total_i
+
+    O = torch.from_numpy(wl.object0.astype(np.complex64)).cuda().requires_grad_(True)
+    P = torch.from_numpy(wl.probe0.astype(np.complex64)).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([O, P], lr=lr)
+    rng = np.random.default_rng([wl.seed, 9])
+    adam_curve = [ferr(O.detach(), P.detach())]
+    adam_s = 0.0
+    for _ in range(epochs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        perm = rng.permutation(wl.count)
+        for b in range(0, wl.count, minibatch):
+            opt.zero_grad(set_to_none=True)
+            amplitude_loss(eng, O, P, perm[b:b + minibatch]).backward()
+            opt.step()
+        torch.cuda.synchronize()
+        adam_s += time.perf_counter() - t0
+        adam_curve.append(ferr(O.detach(), P.detach()))
+    target = adam_curve[-1]
+    epie_curve = [ferr(eng.get_object(device=True), eng.get_probe(device=True))]
+    epie_s, match, match_s = 0.0, None, None
+    for k in range(1, max_sweeps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.sweep(1)
+        torch.cuda.synchronize()
+        epie_s += time.perf_counter() - t0
+        epie_curve.append(ferr(eng.get_object(device=True), eng.get_probe(device=True)))
+        if match is None and epie_curve[-1] <= target:
+            match, match_s = k, epie_s
+    pick = lambda c, step: [round(float(v), 6) for v in c[::step]] + ([round(float(c[-1]), 6)] if (len(c) - 1) % step else [])
+    return {
+        "workload": "128x128 patterns, 60x60 raster (3600 positions), 1024x1024 object, start: flat object, "
+                    "Gaussian probe",
+        "metric": "full-data Fourier error sum_j sum_k (|F(P S_j O)| - sqrt I)^2 / sum I",
+        "adam": {"epochs": epochs, "minibatch": minibatch, "lr": lr, "final_error": round(float(target), 6),
+                 "seconds": round(adam_s, 3), "error_every_10_epochs": pick(adam_curve, 10)},
+        "epie": {"sweeps_to_reach_adam_final": match,
+                 "seconds_to_reach_adam_final": None if match_s is None else round(match_s, 4),
+                 "sweeps": max_sweeps, "final_error": round(float(epie_curve[-1]), 6),
+                 "error_every_5_sweeps": pick(epie_curve, 5)},
+    }
+
+
 def cpu_baseline(cfg_id, budget_s):
     """The FP64 oracle on the host: coloured sweep over the same workload's
     first batches until ``budget_s`` seconds of work are done."""
@@ -248,6 +313,8 @@ def main():
     ap.add_argument("--steps-256", type=int, default=3)
     ap.add_argument("--no-multi", action="store_true", help="skip the 16 independent scans advanced together")
     ap.add_argument("--steps-multi", type=int, default=3)
+    ap.add_argument("--adam-vs-epie", action="store_true",
+                    help="only compare gradient reconstruction (Adam) with ePIE at equal Fourier error")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -262,6 +329,9 @@ def main():
             torch.neg(x, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "neg copy", "bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4}))
+        return
+    if args.adam_vs_epie:
+        print(json.dumps({"adam_vs_epie": run_adam_vs_epie(100, 512, 1e-2, 100)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the reconstruction of one scan is not split across GPUs "
