@@ -175,8 +175,9 @@ int ptyc_sweep(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
  * (several scans of uneven size and pattern size at once).  Every context
  * follows its own default schedule, exactly as ptyc_sweep(ctx, n_sweeps,
  * NULL, ...) would, and produces the same bytes; a step advances every
- * unfinished context by one batch and, per pattern size, launches each
- * stage once for all of them, so small batches share the GPU.  All contexts
+ * unfinished context by one batch and launches each stage once for all
+ * contexts of pattern size 64, 128 or 256 (and once per size for 16 and
+ * 32), so small batches share the GPU.  All contexts
  * must use the same device and stream; n_ctx <= PTYC_MULTI_MAX.  err_out:
  * NULL or n_ctx * n_sweeps doubles (context-major) receiving each sweep's
  * running Fourier error (this synchronises).  The call synchronises the

@@ -34,7 +34,7 @@ struct ptyc_ctx {
     std::string err;
     int form = kFormBatch;          // launch form of a sweep
     int capacity = 0;               // co-resident workgroups of the persistent kernel
-    Shape sb{}, sp{};               // work split of the per-batch and persistent forms
+    Shape sb{}, sp{}, sm{};         // work split of the per-batch, persistent and mixed-size launches
 
     // device state
     DevBuf obj, probe, tw;
@@ -195,7 +195,7 @@ void default_schedule(const ptyc_ctx* c, int64_t sweep, std::vector<int64_t>& or
 
 const Shape& shape_of(const ptyc_ctx* c) { return c->form == kFormPersistent ? c->sp : c->sb; }
 int max_row_blocks(const ptyc_ctx* c) { return std::max(c->sb.row_blocks, c->sp.row_blocks); }
-int max_col_blocks(const ptyc_ctx* c) { return std::max(c->sb.col_blocks, c->sp.col_blocks); }
+int max_col_blocks(const ptyc_ctx* c) { return std::max({c->sb.col_blocks, c->sp.col_blocks, c->sm.col_blocks}); }
 int max_probe_blocks(const ptyc_ctx* c) { return std::max(c->sb.probe_blocks, c->sp.probe_blocks); }
 
 float* pmax_half(const ptyc_ctx* c, int k) { return (float*)c->pmax_part.p + (size_t)k * max_probe_blocks(c); }
@@ -218,6 +218,7 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.err_part = (double*)c->err_part.p;
     a.alpha = c->cfg.alpha;
     a.beta = c->cfg.beta;
+    a.n = c->cfg.n;
     a.mask = (const unsigned char*)c->mask.p;
     return a;
 }
@@ -336,6 +337,7 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     c->stream = (hipStream_t)hip_stream;
     c->sb = shape_for(cfg->n, kFormBatch);
     c->sp = shape_for(cfg->n, kFormPersistent);
+    c->sm = shape_for(cfg->n, kFormMixed);
     c->dev_limit = env_limit();
     c->colouring = new Colouring(cfg->n, max_batch_of(c));
     c->ingest.frame_h = c->ingest.frame_w = cfg->n;
@@ -690,10 +692,9 @@ int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
     return PTYC_OK;
 }
 
-// the error-metric reduction of sweep s of a plan (batch-form layout when
-// batch_layout, else the context's form)
-int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, bool batch_layout) {
-    const int gc = batch_layout ? c->sb.col_blocks : shape_of(c).col_blocks;
+// the error-metric reduction of sweep s of a plan whose column stage wrote
+// gc partials per position
+int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, int gc) {
     const int64_t* ord = (const int64_t*)c->order.p + (size_t)s * p.olen;
     HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, p.olen * gc, ord, p.olen, (const double*)c->sum_i.p,
                                 (double*)c->err_dev.p + s, c->stream));
@@ -824,7 +825,7 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                 }
             }
         }
-        if (err_out && (rc = launch_sweep_error(c, p, s, false)) != PTYC_OK) return rc;
+        if (err_out && (rc = launch_sweep_error(c, p, s, shape_of(c).col_blocks)) != PTYC_OK) return rc;
     }
     c->sweeps_done += n_sweeps;
     if (err_out) {
@@ -855,29 +856,31 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
     for (int i = 0; i < n_ctx; ++i)
         if (plans[(size_t)i].olen > 0 && (rc = stage_plan(ctxs[i], plans[(size_t)i], n_sweeps, kFormBatch)) != PTYC_OK)
             return rc;
-    // one step advances every unfinished context by one batch; per pattern
-    // size, each step is three launches covering all of that size's batches.
-    // (The sizes share nothing, but running them on streams of their own was
-    // measured slower: each kernel boundary's cache maintenance then lands
-    // in the middle of the other streams' kernels.)
+    // one step advances every unfinished context by one batch.  The pattern
+    // sizes 64, 128 and 256 share three launches per step (mixed-size
+    // kernels); 16 and 32 get three launches per size.  (Running the sizes
+    // on streams of their own instead was measured slower: each kernel
+    // boundary's cache maintenance then lands in the middle of the other
+    // streams' kernels.)
     int64_t steps = 0;
     for (int i = 0; i < n_ctx; ++i) steps = std::max(steps, (int64_t)n_sweeps * plans[(size_t)i].nb);
-    constexpr int kSizes[] = {16, 32, 64, 128, 256};
+    constexpr int kGroups[] = {0, 16, 32};        // 0: the mixed-size group
     std::vector<BatchArgs> tab;
     struct Launch {
-        int n;
+        int n;                                    // 0: mixed sizes
         size_t first;
         int count;
         std::vector<std::pair<int, int>> ends;    // (context, sweep) whose sweep ends with this launch
     };
     std::vector<Launch> work;                     // in step order
     for (int64_t k = 0; k < steps; ++k) {
-        for (int n : kSizes) {
-            Launch L{n, tab.size(), 0, {}};
+        for (int grp : kGroups) {
+            Launch L{grp, tab.size(), 0, {}};
             for (int i = 0; i < n_ctx; ++i) {
                 ptyc_ctx* c = ctxs[i];
                 const Plan& p = plans[(size_t)i];
-                if (c->cfg.n != n || p.olen == 0 || k >= (int64_t)n_sweeps * p.nb) continue;
+                const bool in = grp == 0 ? mixed_n(c->cfg.n) : c->cfg.n == grp;
+                if (!in || p.olen == 0 || k >= (int64_t)n_sweeps * p.nb) continue;
                 const int s = (int)(k / p.nb);
                 const int64_t b = k % p.nb;
                 BatchArgs a = base_args(c);
@@ -902,11 +905,17 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
         HIPCHK(c0, hipStreamSynchronize(c0->stream));
     }
     for (const Launch& L : work) {
-        HIPCHK(c0, launch_batch_multi(L.n, (const BatchArgs*)c0->multi.p + L.first, tab.data() + L.first, L.count,
-                                      c0->stream));
+        const BatchArgs* dev = (const BatchArgs*)c0->multi.p + L.first;
+        if (L.n == 0)
+            HIPCHK(c0, launch_batch_mixed(dev, tab.data() + L.first, L.count, c0->stream));
+        else
+            HIPCHK(c0, launch_batch_multi(L.n, dev, tab.data() + L.first, L.count, c0->stream));
         if (err_out)
-            for (auto [i, s] : L.ends)
-                if ((rc = launch_sweep_error(ctxs[i], plans[(size_t)i], s, true)) != PTYC_OK) return rc;
+            for (auto [i, s] : L.ends) {
+                ptyc_ctx* c = ctxs[i];
+                const int gc = L.n == 0 ? c->sm.col_blocks : c->sb.col_blocks;
+                if ((rc = launch_sweep_error(c, plans[(size_t)i], s, gc)) != PTYC_OK) return rc;
+            }
     }
     for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps_done += n_sweeps;
     if (err_out) {

@@ -36,6 +36,7 @@ struct BatchArgs {
     const unsigned char* mask;  // [n][n] 1 = measured detector pixel; nullptr: all measured
     const int64_t* boffs;     // if set: off and bsize are read from boffs[batch], boffs[batch + 1]
     int batch;
+    int n;                    // pattern size (read by the mixed-size kernels)
 };
 
 // How raw detector frames become stored amplitudes.
@@ -53,7 +54,7 @@ struct IngestSpec {
 enum : int { kModeEpie = 0, kModeGrad = 1, kModeLoss = 2 };
 
 // Launch forms of a sweep.
-enum : int { kFormBatch = 1, kFormPersistent = 2, kFormGraph = 3 };
+enum : int { kFormBatch = 1, kFormPersistent = 2, kFormGraph = 3, kFormMixed = 4 };
 
 // Work split per pattern size and launch form.
 struct Shape {
@@ -83,6 +84,11 @@ hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t 
 // size n (three launches): dev_tab on the device, host_tab the same
 // descriptors on the host (for the grid layout); count <= kMultiMax
 constexpr int kMultiMax = 64;
+// pattern sizes the mixed-size kernels serve (64, 128, 256)
+bool mixed_n(int n);
+// one batch of each of `count` independent reconstructions of any sizes
+// that mixed_n accepts, three launches in all (the layout of kFormMixed)
+hipError_t launch_batch_mixed(const BatchArgs* dev_tab, const BatchArgs* host_tab, int count, hipStream_t s);
 hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* host_tab, int count,
                               hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel

@@ -507,6 +507,88 @@ __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
     stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds, dl, red);
 }
 
+// Mixed pattern sizes in one launch per stage.  Every size in {64, 128,
+// 256} gets a tile with the same workgroup size (kMixRowNT threads in the
+// row and column stages, kMixInvNT in the inverse stage), so one kernel
+// serves all of them; a workgroup finds its descriptor and branches (the
+// descriptor is uniform) to the stage of that size.  The tiles change how
+// rows, columns and slots are grouped into workgroups, not the arithmetic
+// of any element, and the partial-maximum layouts do not depend on the
+// tile: the results equal those of the per-size kernels.
+constexpr int kMixRowNT = 256, kMixInvNT = 512;
+template <int N> struct MixTile;
+template <> struct MixTile<64>  { static constexpr int RB = 32, R = 4, S = 16; };
+template <> struct MixTile<128> { static constexpr int RB = 32, R = 2, S = 32; };
+template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32; };
+template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
+template <int N> constexpr int kMixInvLds = MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE;
+template <int N> constexpr int kMixInvDl = MixTile<N>::S * MixTile<N>::R * N;
+constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+constexpr int kMixRowLdsMax = cmax3(kMixRowLds<64>, kMixRowLds<128>, kMixRowLds<256>);
+constexpr int kMixInvLdsMax = cmax3(kMixInvLds<64>, kMixInvLds<128>, kMixInvLds<256>);
+constexpr int kMixInvDlMax = cmax3(kMixInvDl<64>, kMixInvDl<128>, kMixInvDl<256>);
+
+template <int N>
+__device__ __forceinline__ void mix_rows_fwd(const BatchArgs& a, int local, cf* lds, float* red) {
+    using g = RowG<N, MixTile<N>::RB>;
+    static_assert(g::NT == kMixRowNT, "mixed row tile");
+    stage_rows_fwd<N, MixTile<N>::RB>(a, local / g::G, local % g::G, lds, red);
+}
+
+template <int N>
+__device__ __forceinline__ void mix_cols(const BatchArgs& a, int local, cf* lds, double* red) {
+    using g = ColG<N, MixTile<N>::RB>;
+    static_assert(g::NT == kMixRowNT, "mixed column tile");
+    stage_cols<N, MixTile<N>::RB>(a, local / g::GC, local % g::GC, lds, red);
+}
+
+template <int N>
+__device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* lds, cf* dl, float* red) {
+    using g = InvG<N, MixTile<N>::R, MixTile<N>::S>;
+    static_assert(g::NT == kMixInvNT, "mixed inverse tile");
+    stage_rows_inv<N, g::R, g::S>(a, local, lds, dl, red);
+}
+
+__global__ __launch_bounds__(kMixRowNT) void k_rows_fwd_mix(MultiArgs m) {
+    __shared__ cf lds[kMixRowLdsMax];
+    __shared__ float red[kMixRowNT / kWave];
+    const int i = multi_find(m);
+    const BatchArgs a = m.tab[i];
+    const int local = (int)blockIdx.x - m.start[i];
+    switch (a.n) {
+        case 64: mix_rows_fwd<64>(a, local, lds, red); break;
+        case 128: mix_rows_fwd<128>(a, local, lds, red); break;
+        case 256: mix_rows_fwd<256>(a, local, lds, red); break;
+    }
+}
+
+__global__ __launch_bounds__(kMixRowNT) void k_cols_mix(MultiArgs m) {
+    __shared__ cf lds[kMixRowLdsMax];
+    __shared__ double red[kMixRowNT / kWave];
+    const int i = multi_find(m);
+    const BatchArgs a = m.tab[i];
+    const int local = (int)blockIdx.x - m.start[i];
+    switch (a.n) {
+        case 64: mix_cols<64>(a, local, lds, red); break;
+        case 128: mix_cols<128>(a, local, lds, red); break;
+        case 256: mix_cols<256>(a, local, lds, red); break;
+    }
+}
+
+__global__ __launch_bounds__(kMixInvNT) void k_rows_inv_mix(MultiArgs m) {
+    __shared__ cf lds[kMixInvLdsMax];
+    __shared__ cf dl[kMixInvDlMax];
+    __shared__ float red[kMixInvNT / kWave];
+    const int i = multi_find(m);
+    const BatchArgs a = m.tab[i];
+    const int local = (int)blockIdx.x - m.start[i];
+    switch (a.n) {
+        case 64: mix_rows_inv<64>(a, local, lds, dl, red); break;
+        case 128: mix_rows_inv<128>(a, local, lds, dl, red); break;
+        case 256: mix_rows_inv<256>(a, local, lds, dl, red); break;
+    }
+}
+
 // Mean of K equally shaped complex arrays, written back to all of them
 // (summed in list order, so the result does not depend on the launch).
 struct MeanArgs {
@@ -679,9 +761,18 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
 }
 
 // ---------------------------------------------------------------- host side
+constexpr int mix_tile_rb(int n) {
+    return n == 64 ? MixTile<64>::RB : n == 128 ? MixTile<128>::RB : n == 256 ? MixTile<256>::RB : 0;
+}
+constexpr int mix_tile_r(int n) {
+    return n == 64 ? MixTile<64>::R : n == 128 ? MixTile<128>::R : n == 256 ? MixTile<256>::R : 0;
+}
 template <int N>
 Shape shape_n(int form) {
     if (form == kFormPersistent) return Shape{kWinParts<N>, N / PTile<N>::B, kProbeParts<N>};
+    if constexpr (N >= 64) {
+        if (form == kFormMixed) return Shape{kWinParts<N>, N / MixTile<N>::RB, kProbeParts<N>};
+    }
     return Shape{kWinParts<N>, N / Tile<N>::CB, kProbeParts<N>};
 }
 
@@ -865,6 +956,26 @@ hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* 
                               hipStream_t s) {
     PTYC_DISPATCH(n, batch_multi_n<N>(dev_tab, host_tab, count, s));
     return hipErrorInvalidValue;
+}
+
+bool mixed_n(int n) { return n == 64 || n == 128 || n == 256; }
+
+hipError_t launch_batch_mixed(const BatchArgs* dev_tab, const BatchArgs* host_tab, int count, hipStream_t s) {
+    if (count <= 0 || count > kMultiMax) return hipErrorInvalidValue;
+    MultiArgs mr{dev_tab, count, {}}, mi{dev_tab, count, {}};
+    mr.start[0] = mi.start[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        const int n = host_tab[i].n;
+        if (!mixed_n(n) || host_tab[i].bsize < 0) return hipErrorInvalidValue;
+        mr.start[i + 1] = mr.start[i] + n / mix_tile_rb(n) * host_tab[i].bsize;
+        mi.start[i + 1] = mi.start[i] + n / mix_tile_r(n);
+    }
+    if (mr.start[count] > 0) {
+        hipLaunchKernelGGL(k_rows_fwd_mix, dim3(mr.start[count]), dim3(kMixRowNT), 0, s, mr);
+        hipLaunchKernelGGL(k_cols_mix, dim3(mr.start[count]), dim3(kMixRowNT), 0, s, mr);
+    }
+    hipLaunchKernelGGL(k_rows_inv_mix, dim3(mi.start[count]), dim3(kMixInvNT), 0, s, mi);
+    return hipGetLastError();
 }
 
 hipError_t launch_mean(void* const* ptrs, int k, int64_t count_c64, hipStream_t s) {
