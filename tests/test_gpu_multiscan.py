@@ -81,6 +81,27 @@ def _first_schedule(wl):
     return e.get_schedule()
 
 
+def test_multi_small_and_mixed_sizes_together():
+    """32 px contexts take the per-size launches and 64/128/256 px the
+    mixed-size ones in the same call; every context still equals its own
+    sweeps bit for bit, and its error agrees."""
+    from paper_2308_10674_amd import sweep_multi
+    scans = _scans()
+    for k, (n, side) in enumerate([(32, 8), (32, 5)]):
+        step = max(1, int(round(0.094 * n)))
+        cen = np.stack(np.meshgrid(np.arange(side), np.arange(side), indexing="ij"), -1).reshape(-1, 2) * step
+        h, w, corners = sim.object_extent(cen, n, 16)
+        scans.append(sim.make_workload(n, None, 10.0, 0.05, corners, 1e6, 700 + k, h=h, w=w))
+    together = [engine_for(wl) for wl in scans]
+    err_m = sweep_multi(together, 2, errors=True)
+    for k, (wl, e_tog) in enumerate(zip(scans, together)):
+        e_alone = engine_for(wl)
+        err_a = e_alone.sweep(2, errors=True)
+        np.testing.assert_array_equal(e_tog.get_object(), e_alone.get_object(), err_msg=f"n{wl.n}")
+        np.testing.assert_array_equal(e_tog.get_probe(), e_alone.get_probe(), err_msg=f"n{wl.n}")
+        np.testing.assert_allclose(err_m[k], err_a, rtol=1e-13)
+
+
 def test_multi_rejects_bad_lists():
     from paper_2308_10674_amd import PtycError, sweep_multi
     scans = _scans()[:2]
