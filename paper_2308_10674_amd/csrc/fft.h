@@ -130,12 +130,46 @@ __host__ __device__ inline void dft(cf* v) {
 
 // Factorisation N = N1 * N2 used for each supported pattern size.
 // T = N2 threads cooperate on one length-N transform; each holds N1 points.
+// L = 1: pass B runs N1/N2 DFTs of length N2 in each thread (N1 >= N2).
+// L = 2: N2 = 2 N1 and every DFT of length N2 of pass B is shared by a pair
+// of lanes (t, t ^ 1): each runs a length-N1 DFT of the even or the odd
+// inputs, the odd lane twiddles by W_N2^k, and the pair swaps halves
+// (X[k] = E[k] + W^k O[k], X[k + N1] = E[k] - W^k O[k]).  Fewer points per
+// thread means twice the threads per line, which is what a batch of a few
+// dozen patterns needs to fill the chip.
+// out(t, i): the index of the spectrum value thread t holds in v[i] after
+// pass B (and must hold before the inverse of pass B).
 template <int N> struct Fact;
-template <> struct Fact<16>  { static constexpr int N1 = 4,  N2 = 4; };
-template <> struct Fact<32>  { static constexpr int N1 = 8,  N2 = 4; };
-template <> struct Fact<64>  { static constexpr int N1 = 8,  N2 = 8; };
-template <> struct Fact<128> { static constexpr int N1 = 16, N2 = 8; };
-template <> struct Fact<256> { static constexpr int N1 = 16, N2 = 16; };
+template <int N1_, int N2_> struct FactL1 {
+    static constexpr int N1 = N1_, N2 = N2_, L = 1;
+    static_assert(N1 % N2 == 0, "pass B groups");
+    __host__ __device__ static inline int out(int t, int i) { return (t + N2 * (i / N2)) + N1 * (i % N2); }
+};
+template <int N1_> struct FactL2 {
+    static constexpr int N1 = N1_, N2 = 2 * N1_, L = 2;
+    static_assert(N2 == 16, "the pair twiddles are written for N2 = 16");
+    __host__ __device__ static inline int out(int t, int i) { return (t >> 1) + N1 * i + N1 * N1 * (t & 1); }
+};
+template <> struct Fact<16>  : FactL1<4, 4> {};
+template <> struct Fact<32>  : FactL1<8, 4> {};
+template <> struct Fact<64>  : FactL1<8, 8> {};
+template <> struct Fact<128> : FactL2<8> {};
+template <> struct Fact<256> : FactL1<16, 16> {};
+
+// multiply by W_16^k of direction DIR, k < 8 (exact constants)
+template <int DIR>
+__host__ __device__ inline cf w16(cf v, int k) {
+    switch (k) {
+        case 1: return twc<DIR>(v, kC8, kS8);
+        case 2: return twc<DIR>(v, kR2, kR2);
+        case 3: return twc<DIR>(v, kS8, kC8);
+        case 4: return rot<DIR>(v);
+        case 5: return twc<DIR>(v, -kS8, kC8);
+        case 6: return twc<DIR>(v, -kR2, kR2);
+        case 7: return twc<DIR>(v, -kC8, kS8);
+        default: return v;
+    }
+}
 
 // LDS exchange buffer of one length-N line: Z[k1][n2] at k1*(N2+1) + n2,
 // padded to an odd number of complex slots per line.
@@ -162,10 +196,10 @@ __host__ __device__ inline void passA_to_lds(cf* v, cf* z, int t, const cf* __re
     }
 }
 
-// Pass B.  Thread t handles k1 = t + N2 m, m < N1/N2.
+// Pass B with L = 1.  Thread t handles k1 = t + N2 m, m < N1/N2.
 // Out: v[m N2 + k2] = X[(t + N2 m) + N1 k2].
 template <int N, int DIR>
-__host__ __device__ inline void passB_from_lds(cf* v, const cf* z, int t) {
+__host__ __device__ inline void passB1_from_lds(cf* v, const cf* z, int t) {
     constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
 #pragma unroll
     for (int m = 0; m < N1 / N2; ++m) {
@@ -179,11 +213,11 @@ __host__ __device__ inline void passB_from_lds(cf* v, const cf* z, int t) {
     }
 }
 
-// Inverse of pass B: from v[m N2 + k2] = X[(t + N2 m) + N1 k2] to
-// Z[k1][n2] = W_N^(DIR n2 k1 ...) * sum_k2 X[k1 + N1 k2] W_N2^(n2 k2) for the
-// transform direction DIR (the conjugate of the forward direction).
+// Inverse of pass B with L = 1: from v[m N2 + k2] = X[(t + N2 m) + N1 k2]
+// to Z[k1][n2] = W_N^(DIR n2 k1) * sum_k2 X[k1 + N1 k2] W_N2^(DIR n2 k2) for
+// the transform direction DIR (the conjugate of the forward direction).
 template <int N, int DIR>
-__host__ __device__ inline void passBinv_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+__host__ __device__ inline void passB1inv_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
     constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
 #pragma unroll
     for (int m = 0; m < N1 / N2; ++m) {
@@ -201,6 +235,62 @@ __host__ __device__ inline void passBinv_to_lds(cf* v, cf* z, int t, const cf* _
     }
 }
 
+// Pass B with L = 2, the part each lane does alone: thread t = 2 k1 + h
+// reads Z[k1][2 m + h], m < N1, runs the length-N1 DFT (E for h = 0, O for
+// h = 1) and the odd lane multiplies by W_N2^k.
+template <int N, int DIR>
+__host__ __device__ inline void passB2_local(cf* v, const cf* z, int t) {
+    constexpr int N1 = Fact<N>::N1;
+    const int k1 = t >> 1, h = t & 1;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) v[m] = z[Lds<N>::at(k1, 2 * m + h)];
+    dft<N1, DIR>(v);
+    if (h) {
+#pragma unroll
+        for (int k = 1; k < N1; ++k) v[k] = w16<DIR>(v[k], k);
+    }
+}
+
+// The pair's combination, p = the partner lane's v: the even lane keeps
+// E + W O = X[k1 + N1 k], the odd lane E - W O = X[k1 + N1 (k + N1)].
+template <int N>
+__host__ __device__ inline void passB2_combine(cf* v, const cf* p, int t) {
+    const float sg = (t & 1) ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < Fact<N>::N1; ++i) v[i] = p[i] + sg * v[i];
+}
+
+// Inverse of pass B with L = 2, first the pair step: with p = the partner's
+// v (the even lane holds X[k1 + N1 k], the odd lane X[k1 + N1 (k + N1)]),
+// the even lane forms X[k] + X[k + N1] and the odd lane
+// (X[k] - X[k + N1]) W_N2^(DIR k).
+template <int N, int DIR>
+__host__ __device__ inline void passB2inv_combine(cf* v, const cf* p, int t) {
+    const float sg = (t & 1) ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < Fact<N>::N1; ++i) v[i] = p[i] + sg * v[i];
+    if (t & 1) {
+#pragma unroll
+        for (int k = 1; k < Fact<N>::N1; ++k) v[k] = w16<DIR>(v[k], k);
+    }
+}
+
+// ... then each lane alone: the length-N1 DFT gives Z'[k1][2 m + h], which
+// is twiddled by W_N^(DIR n2 k1) into the LDS line.
+template <int N, int DIR>
+__host__ __device__ inline void passB2inv_local_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+    constexpr int N1 = Fact<N>::N1;
+    const int k1 = t >> 1, h = t & 1;
+    dft<N1, DIR>(v);
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        const int n2 = 2 * m + h;
+        cf w = tw[n2 * k1];
+        if (DIR > 0) w.y = -w.y;
+        z[Lds<N>::at(k1, n2)] = cmul(v[m], w);
+    }
+}
+
 // Inverse of pass A: thread t = n2 reads Z[k1][t], k1 < N1, and ends with
 // v[n1] = x[N2 n1 + t].
 template <int N, int DIR>
@@ -209,6 +299,41 @@ __host__ __device__ inline void passAinv_from_lds(cf* v, const cf* z, int t) {
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) v[k1] = z[Lds<N>::at(k1, t)];
     dft<N1, DIR>(v);
+}
+
+// Device forms of pass B and its inverse.  XOR is the lane distance of the
+// two threads t and t ^ 1 of a line (1 when t is the fastest thread index,
+// the column tile width when the columns are).
+template <int XOR>
+__device__ inline cf lane_swap(cf v) {
+    static_assert(XOR > 0 && XOR < 64 && (XOR & (XOR - 1)) == 0, "lane distance");
+    return cf{__shfl_xor(v.x, XOR, 64), __shfl_xor(v.y, XOR, 64)};
+}
+
+template <int N, int DIR, int XOR>
+__device__ inline void passB_from_lds(cf* v, const cf* z, int t) {
+    if constexpr (Fact<N>::L == 1) {
+        passB1_from_lds<N, DIR>(v, z, t);
+    } else {
+        passB2_local<N, DIR>(v, z, t);
+        cf p[Fact<N>::N1];
+#pragma unroll
+        for (int i = 0; i < Fact<N>::N1; ++i) p[i] = lane_swap<XOR>(v[i]);
+        passB2_combine<N>(v, p, t);
+    }
+}
+
+template <int N, int DIR, int XOR>
+__device__ inline void passBinv_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+    if constexpr (Fact<N>::L == 1) {
+        passB1inv_to_lds<N, DIR>(v, z, t, tw);
+    } else {
+        cf p[Fact<N>::N1];
+#pragma unroll
+        for (int i = 0; i < Fact<N>::N1; ++i) p[i] = lane_swap<XOR>(v[i]);
+        passB2inv_combine<N, DIR>(v, p, t);
+        passB2inv_local_to_lds<N, DIR>(v, z, t, tw);
+    }
 }
 
 }  // namespace ptyc

@@ -86,7 +86,9 @@ __device__ inline double block_sum(double v, double* sh) {
 // ---------------------------------------------------------------- tiles
 // Forward row stage: RB rows of one position per workgroup; column stage: CB
 // columns.  Small tiles spread a position over many compute units (a batch
-// holds only a few dozen positions, so the stages are latency-bound).
+// holds only a few dozen positions, so the stages are latency-bound).  At
+// 128 px (16 threads per line) 8 rows and 16 columns measured best; 8
+// columns per workgroup were markedly slower.
 #ifndef PTYC_RB64
 #define PTYC_RB64 16
 #endif
@@ -94,7 +96,7 @@ __device__ inline double block_sum(double v, double* sh) {
 #define PTYC_CB64 16
 #endif
 #ifndef PTYC_RB128
-#define PTYC_RB128 16
+#define PTYC_RB128 8
 #endif
 #ifndef PTYC_CB128
 #define PTYC_CB128 16
@@ -154,6 +156,8 @@ template <int N, int CB> struct ColG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
     static constexpr int GC = N / CB, NT = CB * T;
     static_assert(N % CB == 0 && NT % kWave == 0, "column tile");
+    // a lane pair of pass B (L = 2) is CB lanes apart and must share a wave
+    static_assert(Fact<N>::L == 1 || 2 * CB <= kWave, "column tile too wide for lane pairs");
 };
 template <int N, int R_ = ITile<N>::R, int S_ = ITile<N>::S> struct InvG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
@@ -196,12 +200,10 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
     cf* z = lds + rl * Lds<N>::LINE;
     passA_to_lds<N, -1>(v, z, t, a.tw);
     __syncthreads();
-    passB_from_lds<N, -1>(v, z, t);
+    passB_from_lds<N, -1, 1>(v, z, t);
     cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
 #pragma unroll
-    for (int mm = 0; mm < g::N1 / g::N2; ++mm)
-#pragma unroll
-        for (int k2 = 0; k2 < g::N2; ++k2) srow[(t + g::N2 * mm) + g::N1 * k2] = v[mm * g::N2 + k2];
+    for (int i = 0; i < g::N1; ++i) srow[Fact<N>::out(t, i)] = v[i];
     m = wave_max(m);
     if (threadIdx.x % kWave == 0) a.winmax[slot * kWinParts<N> + rb * (g::NT / kWave) + threadIdx.x / kWave] = m;
 }
@@ -224,17 +226,15 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
     for (int n1 = 0; n1 < g::N1; ++n1) v[n1] = base[(size_t)(g::N2 * n1 + t) * N];
     bool valid[g::N1];
 #pragma unroll
-    for (int mm = 0; mm < g::N1 / g::N2; ++mm)
-#pragma unroll
-        for (int k2 = 0; k2 < g::N2; ++k2) {
-            const int row = (t + g::N2 * mm) + g::N1 * k2;
-            amp[mm * g::N2 + k2] = ampb[(size_t)row * N];
-            valid[mm * g::N2 + k2] = a.mask == nullptr || a.mask[row * N + c] != 0;
-        }
+    for (int i = 0; i < g::N1; ++i) {
+        const int row = Fact<N>::out(t, i);
+        amp[i] = ampb[(size_t)row * N];
+        valid[i] = a.mask == nullptr || a.mask[row * N + c] != 0;
+    }
     cf* z = lds + cl * Lds<N>::LINE;
     passA_to_lds<N, -1>(v, z, t, a.tw);
     __syncthreads();
-    passB_from_lds<N, -1>(v, z, t);
+    passB_from_lds<N, -1, CB>(v, z, t);
     float e = 0.f;
 #pragma unroll
     for (int i = 0; i < g::N1; ++i) {
@@ -261,7 +261,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
     }
     if (MODE != kModeLoss) {
         __syncthreads();
-        passBinv_to_lds<N, +1>(v, z, t, a.tw);
+        passBinv_to_lds<N, +1, CB>(v, z, t, a.tw);
         __syncthreads();
         passAinv_from_lds<N, +1>(v, z, t);
 #pragma unroll
@@ -322,10 +322,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 const cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
                 orow = a.obj + (size_t)(p0.x + r) * a.w + p0.y;
 #pragma unroll
-                for (int mm = 0; mm < g::N1 / g::N2; ++mm)
-#pragma unroll
-                    for (int k2 = 0; k2 < g::N2; ++k2)
-                        v[mm * g::N2 + k2] = srow[(t + g::N2 * mm) + g::N1 * k2];
+                for (int i = 0; i < g::N1; ++i) v[i] = srow[Fact<N>::out(t, i)];
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = orow[g::N2 * n1 + t];
             } else {
@@ -350,7 +347,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 wm = group_max<GT>(wm);
                 if (act) om = wm;
             }
-            passBinv_to_lds<N, +1>(v, z, t, a.tw);
+            passBinv_to_lds<N, +1, 1>(v, z, t, a.tw);
             __syncthreads();
             passAinv_from_lds<N, +1>(v, z, t);
             constexpr float inv = 1.0f / (float)(N * N);
@@ -518,7 +515,7 @@ __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
 constexpr int kMixRowNT = 256, kMixInvNT = 512;
 template <int N> struct MixTile;
 template <> struct MixTile<64>  { static constexpr int RB = 32, R = 4, S = 16; };
-template <> struct MixTile<128> { static constexpr int RB = 32, R = 2, S = 32; };
+template <> struct MixTile<128> { static constexpr int RB = 16, R = 1, S = 32; };
 template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32; };
 template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
 template <int N> constexpr int kMixInvLds = MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE;

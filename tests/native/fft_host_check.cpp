@@ -1,6 +1,8 @@
 // Host-side check of the in-register DFTs and the four-step passes of
 // fft.h against a direct O(N^2) double-precision DFT.  Threads of one line
-// are emulated one after the other; the LDS buffer is a plain array.
+// are emulated one after the other; the LDS buffer is a plain array, and a
+// lane pair's swap (pass B with L = 2) is emulated by handing each lane its
+// partner's values.  Also checks that out(t, i) covers every index once.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -61,14 +63,38 @@ static int check_line() {
         for (int n1 = 0; n1 < N1; ++n1) regs[t][n1] = x[N2 * n1 + t];
         passA_to_lds<N, -1>(regs[t].data(), z.data(), t, tw.data());
     }
-    for (int t = 0; t < N2; ++t) {
-        passB_from_lds<N, -1>(regs[t].data(), z.data(), t);
-        for (int m = 0; m < N1 / N2; ++m)
-            for (int k2 = 0; k2 < N2; ++k2) X[(t + N2 * m) + N1 * k2] = regs[t][m * N2 + k2];
+    if constexpr (Fact<N>::L == 1) {
+        for (int t = 0; t < N2; ++t) passB1_from_lds<N, -1>(regs[t].data(), z.data(), t);
+    } else {
+        // lane pairs: every lane's local part first, then each combines with
+        // its partner's local result (what the lane swap delivers on the GPU)
+        for (int t = 0; t < N2; ++t) passB2_local<N, -1>(regs[t].data(), z.data(), t);
+        auto local = regs;
+        for (int t = 0; t < N2; ++t) passB2_combine<N>(regs[t].data(), local[t ^ 1].data(), t);
+    }
+    for (int t = 0; t < N2; ++t)
+        for (int i = 0; i < N1; ++i) X[Fact<N>::out(t, i)] = regs[t][i];
+    {
+        std::vector<int> seen(N, 0);
+        for (int t = 0; t < N2; ++t)
+            for (int i = 0; i < N1; ++i) ++seen[Fact<N>::out(t, i)];
+        for (int k = 0; k < N; ++k)
+            if (seen[k] != 1) {
+                std::printf("line%-4d out() covers index %d %d times\n", N, k, seen[k]);
+                return 1;
+            }
     }
     double ef = direct_err(x, X, -1);
     // inverse back from the pass-B distribution
-    for (int t = 0; t < N2; ++t) passBinv_to_lds<N, +1>(regs[t].data(), z.data(), t, tw.data());
+    if constexpr (Fact<N>::L == 1) {
+        for (int t = 0; t < N2; ++t) passB1inv_to_lds<N, +1>(regs[t].data(), z.data(), t, tw.data());
+    } else {
+        auto held = regs;
+        for (int t = 0; t < N2; ++t) {
+            passB2inv_combine<N, +1>(regs[t].data(), held[t ^ 1].data(), t);
+            passB2inv_local_to_lds<N, +1>(regs[t].data(), z.data(), t, tw.data());
+        }
+    }
     double eb = 0, den = 0;
     for (int t = 0; t < N2; ++t) {
         passAinv_from_lds<N, +1>(regs[t].data(), z.data(), t);
