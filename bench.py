@@ -43,11 +43,17 @@ KERNEL_BYTES = {
 }
 
 
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "fft.h")
+
+
 def kernel_source_hash():
+    """sha256 prefix over the sources the kernels are compiled from."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2308_10674_amd", "csrc", "kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2308_10674_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel, n):

@@ -40,7 +40,7 @@ struct ptyc_ctx {
     DevBuf obj, probe, tw;
     DevBuf sqrt_i, pos, sum_i;       // per position, capacity cap
     int64_t cap = 0, n_loaded = 0;
-    DevBuf scratch, dprobe, winmax;  // per batch slot, capacity slots
+    DevBuf scratch, winmax;          // per batch slot, capacity slots
     int64_t slots = 0;
     DevBuf pmax_part;                // two halves of max_probe_blocks floats (see pmax_cur)
     int pmax_cur = 0;                // the half holding the current probe's partial maxima
@@ -211,7 +211,6 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.pos = (const int2*)c->pos.p;
     a.order = (const int64_t*)c->order.p;
     a.scratch = (cf*)c->scratch.p;
-    a.dprobe = (cf*)c->dprobe.p;
     a.winmax = (float*)c->winmax.p;
     a.pmax_in = pmax_half(c, c->pmax_cur);
     a.pmax_out = pmax_half(c, c->pmax_cur ^ 1);
@@ -386,7 +385,7 @@ void ptyc_destroy(ptyc_ctx* c) {
     if (!c) return;
     if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
-                      &c->dprobe, &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
+                      &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
                       &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging,
                       &c->gorder, &c->goffs};
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -651,7 +650,6 @@ int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
     const size_t nn = (size_t)c->cfg.n * c->cfg.n;
     if (p.max_b > c->slots) {
         if ((rc = ensure(c, c->scratch, (size_t)p.max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
-        if ((rc = ensure(c, c->dprobe, (size_t)p.max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
         if ((rc = ensure(c, c->winmax, (size_t)p.max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
         c->slots = p.max_b;
     }
@@ -705,7 +703,7 @@ int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, int gc) {
 bool same_key(const BatchArgs& x, const BatchArgs& y) {
     return x.obj == y.obj && x.h == y.h && x.w == y.w && x.probe == y.probe && x.tw == y.tw &&
            x.sqrt_i == y.sqrt_i && x.pos == y.pos && x.order == y.order && x.scratch == y.scratch &&
-           x.dprobe == y.dprobe && x.winmax == y.winmax &&
+           x.winmax == y.winmax &&
            x.pmax_in == y.pmax_in && x.pmax_out == y.pmax_out && x.err_part == y.err_part &&
            x.alpha == y.alpha && x.beta == y.beta && x.mask == y.mask && x.boffs == y.boffs;
 }
@@ -1036,7 +1034,6 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
     for (size_t b = 0; b + 1 < off.size(); ++b) max_b = std::max(max_b, off[b + 1] - off[b]);
     if (max_b > c->slots) {
         if ((rc = ensure(c, c->scratch, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
-        if ((rc = ensure(c, c->dprobe, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
         if ((rc = ensure(c, c->winmax, (size_t)max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
         c->slots = max_b;
     }

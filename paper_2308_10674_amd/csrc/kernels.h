@@ -20,7 +20,6 @@ struct BatchArgs {
     int64_t off;              // first order entry of this batch
     int bsize;                // positions in this batch
     cf* scratch;              // [slots][n][n] spectrum exchange between stages
-    cf* dprobe;               // [slots][n][n] per-position probe increments
     float* winmax;            // [slots][Shape::row_blocks] partial max |S_j O|^2, one per forward-stage wave
     // partial maxima of |P|^2 per probe row block, double-buffered: the
     // inverse row stage reads those of P_b from pmax_in and writes those of
