@@ -340,8 +340,8 @@ def main():
         print(json.dumps({"adam_vs_epie": run_adam_vs_epie(100, 512, 1e-2, 100)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the reconstruction of one scan is not split across GPUs "
-              "in this build (see the sharding notes of the design document).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library does not split the reconstruction of one scan "
+              "across GPUs, so --gpus must be 1.", file=sys.stderr)
         sys.exit(2)
 
     r = run_gpu(1, args.steps, args.warmup, args.form)
