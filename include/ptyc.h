@@ -228,6 +228,27 @@ int ptyc_set_form(ptyc_ctx* ctx, int form);
 /* The current launch form (-1 for a NULL context). */
 int ptyc_get_form(const ptyc_ctx* ctx);
 
+/* Tile variants of the per-batch kernels (batch and graph forms).  The three
+ * kernels of a batch can group rows, columns and slots into workgroups in
+ * several ways (ptyc_tile_count variants at the context's pattern size,
+ * variant 0 the default); every variant produces the same object and probe
+ * bit for bit and they differ only in speed.  ptyc_tune times each variant
+ * on `reps` runs of one sweep over the loaded positions, each from the same
+ * state with the same schedule, keeps the fastest, and restores the object,
+ * the probe and the sweep counter, so tuning leaves the reconstruction as it
+ * was.  tile_out (nullable) receives the choice; ms_out (nullable,
+ * PTYC_TILE_MAX entries) each variant's best sweep time in milliseconds (0
+ * for entries past the count).  With no positions loaded nothing is timed
+ * and the current variant is kept.  Synchronises the stream.  Errors:
+ * PTYC_ERR_ARG for reps outside 1..100 or a tile outside
+ * 0..ptyc_tile_count()-1; ptyc_tile_count and ptyc_get_tile return -1 for
+ * a NULL context. */
+#define PTYC_TILE_MAX 8
+int ptyc_tile_count(const ptyc_ctx* ctx);
+int ptyc_set_tile(ptyc_ctx* ctx, int tile);
+int ptyc_get_tile(const ptyc_ctx* ctx);
+int ptyc_tune(ptyc_ctx* ctx, int32_t reps, int32_t* tile_out, double* ms_out);
+
 /* Per-kernel timing.  While enabled, every batch-form kernel is launched
  * with a start and an end event bound to its own dispatch, so the interval
  * is the kernel's execution (as a kernel trace reports it); the persistent

@@ -21,6 +21,7 @@ PTYC_FORM_DEFAULT = 0
 PTYC_FORM_BATCH = 1
 PTYC_FORM_PERSISTENT = 2
 PTYC_FORM_GRAPH = 3
+PTYC_TILE_MAX = 8
 PTYC_KERNEL_ROWS_FWD = 0
 PTYC_KERNEL_COLS = 1
 PTYC_KERNEL_ROWS_INV = 2
@@ -76,6 +77,10 @@ SIGNATURES = {
     "ptyc_profile": (C.c_int, [_P, C.c_int]),
     "ptyc_profile_read": (C.c_int, [_P, C.c_int, _DP, _I64P, _I64P]),
     "ptyc_get_form": (C.c_int, [_P]),
+    "ptyc_tile_count": (C.c_int, [_P]),
+    "ptyc_set_tile": (C.c_int, [_P, C.c_int]),
+    "ptyc_get_tile": (C.c_int, [_P]),
+    "ptyc_tune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "ptyc_num_positions": (C.c_int64, [_P]),
     "ptyc_sweep_count": (C.c_int64, [_P]),
     "ptyc_synchronize": (C.c_int, [_P]),

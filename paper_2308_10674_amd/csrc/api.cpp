@@ -34,7 +34,10 @@ struct ptyc_ctx {
     std::string err;
     int form = kFormBatch;          // launch form of a sweep
     int capacity = 0;               // co-resident workgroups of the persistent kernel
-    Shape sb{}, sp{}, sm{};         // work split of the per-batch, persistent and mixed-size launches
+    Shape sb{}, sp{}, sm{};         // work split of the per-batch (default tile), persistent and mixed-size launches
+    int tile = 0;                   // tile variant of the per-batch kernels (batch and graph forms)
+    Shape st{};                     // work split of that variant
+    int col_blocks_max = 0;         // over every form and variant (error partials per position)
 
     // device state
     DevBuf obj, probe, tw;
@@ -71,7 +74,9 @@ struct ptyc_ctx {
     hipGraphExec_t gexec = nullptr;
     BatchArgs gkey{};
     int64_t g_nb = -1, g_maxb = -1;
+    int g_tile = -1;
     DevBuf gorder, goffs;
+    DevBuf tune_save;                // object and probe saved while ptyc_tune times the variants
 
     // optional per-kernel timing with events on the context's stream
     bool prof = false;
@@ -193,9 +198,9 @@ void default_schedule(const ptyc_ctx* c, int64_t sweep, std::vector<int64_t>& or
     }
 }
 
-const Shape& shape_of(const ptyc_ctx* c) { return c->form == kFormPersistent ? c->sp : c->sb; }
+const Shape& shape_of(const ptyc_ctx* c) { return c->form == kFormPersistent ? c->sp : c->st; }
 int max_row_blocks(const ptyc_ctx* c) { return std::max(c->sb.row_blocks, c->sp.row_blocks); }
-int max_col_blocks(const ptyc_ctx* c) { return std::max({c->sb.col_blocks, c->sp.col_blocks, c->sm.col_blocks}); }
+int max_col_blocks(const ptyc_ctx* c) { return c->col_blocks_max; }
 int max_probe_blocks(const ptyc_ctx* c) { return std::max(c->sb.probe_blocks, c->sp.probe_blocks); }
 
 float* pmax_half(const ptyc_ctx* c, int k) { return (float*)c->pmax_part.p + (size_t)k * max_probe_blocks(c); }
@@ -335,8 +340,12 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     c->cfg = *cfg;
     c->stream = (hipStream_t)hip_stream;
     c->sb = shape_for(cfg->n, kFormBatch);
+    c->st = c->sb;
     c->sp = shape_for(cfg->n, kFormPersistent);
     c->sm = shape_for(cfg->n, kFormMixed);
+    c->col_blocks_max = std::max(c->sp.col_blocks, c->sm.col_blocks);
+    for (int v = 0; v < tile_variants(cfg->n); ++v)
+        c->col_blocks_max = std::max(c->col_blocks_max, shape_for(cfg->n, kFormBatch, v).col_blocks);
     c->dev_limit = env_limit();
     c->colouring = new Colouring(cfg->n, max_batch_of(c));
     c->ingest.frame_h = c->ingest.frame_w = cfg->n;
@@ -387,7 +396,7 @@ void ptyc_destroy(ptyc_ctx* c) {
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
                       &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
                       &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging,
-                      &c->gorder, &c->goffs};
+                      &c->gorder, &c->goffs, &c->tune_save};
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
@@ -423,6 +432,90 @@ int ptyc_set_form(ptyc_ctx* c, int form) {
 }
 
 int ptyc_get_form(const ptyc_ctx* c) { return c ? c->form : -1; }
+
+int ptyc_tile_count(const ptyc_ctx* c) { return c ? tile_variants(c->cfg.n) : -1; }
+
+int ptyc_set_tile(ptyc_ctx* c, int tile) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (tile < 0 || tile >= tile_variants(c->cfg.n)) return fail(c, PTYC_ERR_ARG, "tile variant out of range");
+    c->tile = tile;
+    c->st = shape_for(c->cfg.n, kFormBatch, tile);
+    return PTYC_OK;
+}
+
+int ptyc_get_tile(const ptyc_ctx* c) { return c ? c->tile : -1; }
+
+int ptyc_tune(ptyc_ctx* c, int32_t reps, int32_t* tile_out, double* ms_out) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (reps < 1 || reps > 100) return fail(c, PTYC_ERR_ARG, "reps must be in 1..100");
+    const int nv = tile_variants(c->cfg.n);
+    if (ms_out)
+        for (int v = 0; v < PTYC_TILE_MAX; ++v) ms_out[v] = 0.0;
+    if (c->n_loaded == 0 || nv <= 1) {
+        if (tile_out) *tile_out = c->tile;
+        return PTYC_OK;
+    }
+    // the state a sweep changes: object, probe (and its maxima), sweep counter
+    const size_t ob = (size_t)c->cfg.h * c->cfg.w * sizeof(cf), pb = (size_t)c->cfg.n * c->cfg.n * sizeof(cf);
+    if ((rc = ensure(c, c->tune_save, ob + pb)) != PTYC_OK) return rc;
+    char* save = (char*)c->tune_save.p;
+    HIPCHK(c, hipMemcpyAsync(save, c->obj.p, ob, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(save + ob, c->probe.p, pb, hipMemcpyDeviceToDevice, c->stream));
+    const int64_t done0 = c->sweeps_done;
+    const int form0 = c->form, tile0 = c->tile;
+    const bool prof0 = c->prof;
+    c->prof = false;
+    c->form = kFormBatch;
+    auto restore = [&]() -> int {
+        HIPCHK(c, hipMemcpyAsync(c->obj.p, save, ob, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->probe.p, save + ob, pb, hipMemcpyDeviceToDevice, c->stream));
+        c->sweeps_done = done0;
+        return refresh_probe_max(c);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = tile0;
+    double best_ms = 0.0;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) rc = hip_fail(c, he, "hipEventCreate");
+    for (int v = 0; v < nv && rc == PTYC_OK; ++v) {
+        c->tile = v;
+        c->st = shape_for(c->cfg.n, kFormBatch, v);
+        double vbest = 0.0;
+        for (int r = 0; r < reps && rc == PTYC_OK; ++r) {
+            if ((rc = restore()) != PTYC_OK) break;
+            if ((he = hipEventRecord(e0, c->stream)) != hipSuccess) { rc = hip_fail(c, he, "hipEventRecord"); break; }
+            if ((rc = ptyc_sweep(c, 1, nullptr, 0, nullptr, 0, nullptr)) != PTYC_OK) break;
+            if ((he = hipEventRecord(e1, c->stream)) != hipSuccess) { rc = hip_fail(c, he, "hipEventRecord"); break; }
+            if ((he = hipEventSynchronize(e1)) != hipSuccess) { rc = hip_fail(c, he, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_fail(c, he, "hipEventElapsedTime"); break; }
+            if (r == 0 || ms < vbest) vbest = ms;
+        }
+        if (rc != PTYC_OK) break;
+        if (ms_out && v < PTYC_TILE_MAX) ms_out[v] = vbest;
+        if (v == 0 || vbest < best_ms) {
+            best_ms = vbest;
+            best = v;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->prof = prof0;
+    if (c->poisoned) return rc;
+    const int keep = rc == PTYC_OK ? best : tile0;
+    c->tile = keep;
+    c->st = shape_for(c->cfg.n, kFormBatch, keep);
+    const int rc2 = restore();            // back to the saved state (batch layout)
+    c->form = form0;
+    const int rc3 = rc2 == PTYC_OK ? refresh_probe_max(c) : rc2;   // maxima in the caller's form
+    if (rc == PTYC_OK) rc = rc3;
+    if (rc == PTYC_OK) HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (tile_out) *tile_out = c->tile;
+    return rc;
+}
 
 int ptyc_profile(ptyc_ctx* c, int enable) {
     int rc = usable(c);
@@ -719,14 +812,14 @@ int graph_sweep(ptyc_ctx* c, const Plan& p, int s) {
     BatchArgs a = base_args(c);
     a.order = (const int64_t*)c->gorder.p;
     a.boffs = (const int64_t*)c->goffs.p;
-    if (!c->gexec || c->g_nb != p.nb || c->g_maxb < p.max_b || !same_key(a, c->gkey)) {
+    if (!c->gexec || c->g_nb != p.nb || c->g_maxb < p.max_b || c->g_tile != c->tile || !same_key(a, c->gkey)) {
         if (c->gexec) {
             HIPCHK(c, hipStreamSynchronize(c->stream));
             HIPCHK(c, hipGraphExecDestroy(c->gexec));
             c->gexec = nullptr;
         }
         hipGraph_t g = nullptr;
-        HIPCHK(c, build_sweep_graph(c->cfg.n, a, (int)p.nb, (int)p.max_b, &g));
+        HIPCHK(c, build_sweep_graph(c->cfg.n, c->tile, a, (int)p.nb, (int)p.max_b, &g));
         hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
@@ -736,6 +829,7 @@ int graph_sweep(ptyc_ctx* c, const Plan& p, int s) {
         c->gkey = a;
         c->g_nb = p.nb;
         c->g_maxb = p.max_b;
+        c->g_tile = c->tile;
     }
     HIPCHK(c, hipMemcpyAsync(c->gorder.p, (const int64_t*)c->order.p + (size_t)s * p.olen,
                              (size_t)p.olen * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
@@ -814,12 +908,12 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
                     if ((rc = take_events(c, 6, &e0)) != PTYC_OK) return rc;
                     hipEvent_t ev[6];
                     for (int k = 0; k < 6; ++k) ev[k] = c->ev_pool[e0 + k];
-                    HIPCHK(c, launch_batch(c->cfg.n, a, c->stream, ev));
+                    HIPCHK(c, launch_batch(c->cfg.n, c->tile, a, c->stream, ev));
                     c->marks.push_back({PTYC_KERNEL_ROWS_FWD, e0, e0 + 1, a.bsize});
                     c->marks.push_back({PTYC_KERNEL_COLS, e0 + 2, e0 + 3, a.bsize});
                     c->marks.push_back({PTYC_KERNEL_ROWS_INV, e0 + 4, e0 + 5, a.bsize});
                 } else {
-                    HIPCHK(c, launch_batch(c->cfg.n, a, c->stream));
+                    HIPCHK(c, launch_batch(c->cfg.n, c->tile, a, c->stream));
                 }
             }
         }

@@ -72,11 +72,14 @@ struct SweepCtl {
 };
 
 bool supported_n(int n);
-Shape shape_for(int n, int form);
+// variant: the per-batch tile variant (batch and graph forms; see tile_variants)
+Shape shape_for(int n, int form, int variant = 0);
+// number of tile variants of the per-batch kernels at pattern size n
+int tile_variants(int n);
 
 // ev: NULL, or six events: the start and end of each of the three kernels
 // of the batch, taken from the kernel dispatches themselves
-hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_batch(int n, int variant, const BatchArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 // the partial maxima of |P|^2 of the current probe (no update), into a.pmax_out
 hipError_t launch_probe_reduce(int n, const BatchArgs& a, int form, hipStream_t s);
 // one batch of each of `count` independent reconstructions with pattern
@@ -102,7 +105,7 @@ hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_ba
 // maxima from a.pmax_in; the halves alternate from node to node (every
 // node, empty or not, writes the other half), so after the graph the
 // current maxima are in a.pmax_in when nb is even, else in a.pmax_out.
-hipError_t build_sweep_graph(int n, const BatchArgs& a, int nb, int max_b, hipGraph_t* out);
+hipError_t build_sweep_graph(int n, int variant, const BatchArgs& a, int nb, int max_b, hipGraph_t* out);
 // amplitude loss over one batch of disjoint windows; grad: also accumulate
 // dL/dO into gobj and dL/dP into gprobe
 hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s);

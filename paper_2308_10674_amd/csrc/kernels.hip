@@ -138,6 +138,39 @@ template <> struct ITile<64>  { static constexpr int R = 4, S = 8; };
 template <> struct ITile<128> { static constexpr int R = PTYC_IR128, S = PTYC_IS128; };
 template <> struct ITile<256> { static constexpr int R = PTYC_IR256, S = PTYC_IS256; };
 
+// Tile variants of the per-batch kernels among which ptyc_tune chooses at
+// run time; variant 0 is the default (the macros above).  The variants only
+// group rows, columns and slots into workgroups differently: every row's
+// and column's arithmetic, the order of the slot sum and the layouts of the
+// partial maxima are the same, so all variants produce the same object and
+// probe bit for bit.
+struct TileV {
+    int rb, cb, r, s;
+};
+template <int N> struct Variants;
+template <> struct Variants<16> {
+    static constexpr int K = 1;
+    static constexpr TileV v[K] = {{Tile<16>::RB, Tile<16>::CB, ITile<16>::R, ITile<16>::S}};
+};
+template <> struct Variants<32> {
+    static constexpr int K = 1;
+    static constexpr TileV v[K] = {{Tile<32>::RB, Tile<32>::CB, ITile<32>::R, ITile<32>::S}};
+};
+template <> struct Variants<64> {
+    static constexpr int K = 2;
+    static constexpr TileV v[K] = {{Tile<64>::RB, Tile<64>::CB, ITile<64>::R, ITile<64>::S}, {32, 32, 4, 8}};
+};
+template <> struct Variants<128> {
+    static constexpr int K = 4;
+    static constexpr TileV v[K] = {
+        {Tile<128>::RB, Tile<128>::CB, ITile<128>::R, ITile<128>::S}, {16, 16, 1, 40}, {8, 16, 1, 32}, {16, 16, 1, 32}};
+};
+template <> struct Variants<256> {
+    static constexpr int K = 3;
+    static constexpr TileV v[K] = {
+        {Tile<256>::RB, Tile<256>::CB, ITile<256>::R, ITile<256>::S}, {8, 16, 1, 32}, {16, 32, 1, 32}};
+};
+
 // Tiles of the persistent form: one workgroup size for all stages (B rows
 // or columns in the forward stages; R rows for S slots in the inverse stage).
 template <int N> struct PTile;
@@ -421,9 +454,8 @@ __device__ __forceinline__ BatchArgs resolved(const BatchArgs& a) {
     return r;
 }
 
-template <int N>
-__global__ __launch_bounds__(kRowNT<N>) void k_rows_fwd(BatchArgs a) {
-    constexpr int RB = Tile<N>::RB;
+template <int N, int RB = Tile<N>::RB>
+__global__ __launch_bounds__((RowG<N, RB>::NT)) void k_rows_fwd(BatchArgs a) {
     using g = RowG<N, RB>;
     __shared__ cf lds[RB * Lds<N>::LINE];
     __shared__ float red[g::NT / kWave];
@@ -433,9 +465,8 @@ __global__ __launch_bounds__(kRowNT<N>) void k_rows_fwd(BatchArgs a) {
     stage_rows_fwd<N, RB>(b, slot, blockIdx.x % g::G, lds, red);
 }
 
-template <int N>
-__global__ __launch_bounds__(kColNT<N>) void k_cols(BatchArgs a) {
-    constexpr int CB = Tile<N>::CB;
+template <int N, int CB = Tile<N>::CB>
+__global__ __launch_bounds__((ColG<N, CB>::NT)) void k_cols(BatchArgs a) {
     using g = ColG<N, CB>;
     __shared__ cf lds[CB * Lds<N>::LINE];
     __shared__ double red[g::NT / kWave];
@@ -765,40 +796,58 @@ constexpr int mix_tile_r(int n) {
     return n == 64 ? MixTile<64>::R : n == 128 ? MixTile<128>::R : n == 256 ? MixTile<256>::R : 0;
 }
 template <int N>
-Shape shape_n(int form) {
+Shape shape_n(int form, int variant) {
     if (form == kFormPersistent) return Shape{kWinParts<N>, N / PTile<N>::B, kProbeParts<N>};
     if constexpr (N >= 64) {
         if (form == kFormMixed) return Shape{kWinParts<N>, N / MixTile<N>::RB, kProbeParts<N>};
     }
-    return Shape{kWinParts<N>, N / Tile<N>::CB, kProbeParts<N>};
+    if (variant < 0 || variant >= Variants<N>::K) variant = 0;
+    return Shape{kWinParts<N>, N / Variants<N>::v[variant].cb, kProbeParts<N>};
 }
 
-template <int N>
+template <int N, int V = 0>
 hipError_t batch_n(const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
-    using rg = RowG<N, Tile<N>::RB>;
-    using cg = ColG<N, Tile<N>::CB>;
+    constexpr TileV tv = Variants<N>::v[V];
+    using rg = RowG<N, tv.rb>;
+    using cg = ColG<N, tv.cb>;
+    using ig = InvG<N, tv.r, tv.s>;
+    constexpr auto kr = k_rows_fwd<N, tv.rb>;
+    constexpr auto kc = k_cols<N, tv.cb>;
+    constexpr auto ki = k_rows_inv<N, tv.r, tv.s>;
     if (ev) {
         // ev[2k], ev[2k+1]: the start and end of kernel k, taken from its
         // own dispatch (not from markers between launches)
         if (a.bsize > 0) {
-            hipExtLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, ev[0], ev[1], 0, a);
-            hipExtLaunchKernelGGL(k_cols<N>, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, ev[2], ev[3], 0, a);
+            hipExtLaunchKernelGGL(kr, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, ev[0], ev[1], 0, a);
+            hipExtLaunchKernelGGL(kc, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, ev[2], ev[3], 0, a);
         }
-        hipExtLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, ev[4], ev[5], 0, a);
+        hipExtLaunchKernelGGL(ki, dim3(ig::GI), dim3(ig::NT), 0, s, ev[4], ev[5], 0, a);
         return hipGetLastError();
     }
     if (a.bsize > 0) {
-        hipLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
-        hipLaunchKernelGGL(k_cols<N>, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
+        hipLaunchKernelGGL(kr, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
+        hipLaunchKernelGGL(kc, dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
     }
-    hipLaunchKernelGGL(k_rows_inv<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
+    hipLaunchKernelGGL(ki, dim3(ig::GI), dim3(ig::NT), 0, s, a);
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int V = 0>
+hipError_t batch_v(int variant, const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
+    if constexpr (V < Variants<N>::K) {
+        if (variant == V) return batch_n<N, V>(a, s, ev);
+        return batch_v<N, V + 1>(variant, a, s, ev);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int N, int V = 0>
 hipError_t graph_n(const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
-    using rg = RowG<N, Tile<N>::RB>;
-    using cg = ColG<N, Tile<N>::CB>;
+    constexpr TileV tv = Variants<N>::v[V];
+    using rg = RowG<N, tv.rb>;
+    using cg = ColG<N, tv.cb>;
+    using ig = InvG<N, tv.r, tv.s>;
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return e;
@@ -826,10 +875,10 @@ hipError_t graph_n(const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
         }
         ab.off = 0;
         ab.bsize = 0;
-        e = add(reinterpret_cast<const void*>(&k_rows_fwd<N>), rg::G * max_b, rg::NT, &ab);
-        if (e == hipSuccess) e = add(reinterpret_cast<const void*>(&k_cols<N>), cg::GC * max_b, cg::NT, &ab);
+        e = add(reinterpret_cast<const void*>(&k_rows_fwd<N, tv.rb>), rg::G * max_b, rg::NT, &ab);
+        if (e == hipSuccess) e = add(reinterpret_cast<const void*>(&k_cols<N, tv.cb>), cg::GC * max_b, cg::NT, &ab);
         if (e == hipSuccess)
-            e = add(reinterpret_cast<const void*>(&k_rows_inv<N>), InvG<N>::GI, InvG<N>::NT, &ab);
+            e = add(reinterpret_cast<const void*>(&k_rows_inv<N, tv.r, tv.s>), ig::GI, ig::NT, &ab);
     }
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g);
@@ -837,6 +886,16 @@ hipError_t graph_n(const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
     }
     *out = g;
     return hipSuccess;
+}
+
+template <int N, int V = 0>
+hipError_t graph_v(int variant, const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
+    if constexpr (V < Variants<N>::K) {
+        if (variant == V) return graph_n<N, V>(a, nb, max_b, out);
+        return graph_v<N, V + 1>(variant, a, nb, max_b, out);
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 template <int N>
@@ -934,13 +993,18 @@ hipError_t ingest_n(const float* src, float* dst, double* sum_i, int64_t count, 
 
 bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
-Shape shape_for(int n, int form) {
-    PTYC_DISPATCH(n, shape_n<N>(form));
+Shape shape_for(int n, int form, int variant) {
+    PTYC_DISPATCH(n, shape_n<N>(form, variant));
     return Shape{0, 0, 0};
 }
 
-hipError_t launch_batch(int n, const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
-    PTYC_DISPATCH(n, batch_n<N>(a, s, ev));
+int tile_variants(int n) {
+    PTYC_DISPATCH(n, Variants<N>::K);
+    return 0;
+}
+
+hipError_t launch_batch(int n, int variant, const BatchArgs& a, hipStream_t s, hipEvent_t* ev) {
+    PTYC_DISPATCH(n, batch_v<N>(variant, a, s, ev));
     return hipErrorInvalidValue;
 }
 
@@ -996,9 +1060,9 @@ hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_ba
     return hipErrorInvalidValue;
 }
 
-hipError_t build_sweep_graph(int n, const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
+hipError_t build_sweep_graph(int n, int variant, const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
     if (nb < 0 || max_b <= 0 || !a.boffs || !out) return hipErrorInvalidValue;
-    PTYC_DISPATCH(n, graph_n<N>(a, nb, max_b, out));
+    PTYC_DISPATCH(n, graph_v<N>(variant, a, nb, max_b, out));
     return hipErrorInvalidValue;
 }
 

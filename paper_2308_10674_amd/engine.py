@@ -221,6 +221,28 @@ class Engine:
         return out
 
     @property
+    def tile(self) -> int:
+        """Tile variant of the per-batch kernels (0 .. tile_count - 1)."""
+        return int(L.lib().ptyc_get_tile(self._ctx))
+
+    @tile.setter
+    def tile(self, v):
+        _check(L.lib().ptyc_set_tile(self._ctx, int(v)), self._ctx)
+
+    @property
+    def tile_count(self) -> int:
+        return int(L.lib().ptyc_tile_count(self._ctx))
+
+    def tune(self, reps=3):
+        """Time every tile variant on one sweep of the loaded positions
+        (state restored afterwards) and keep the fastest.  Returns (chosen
+        variant, [best ms per sweep of each variant])."""
+        t = C.c_int32()
+        ms = (C.c_double * L.PTYC_TILE_MAX)()
+        _check(L.lib().ptyc_tune(self._ctx, int(reps), C.byref(t), ms), self._ctx)
+        return int(t.value), [float(ms[i]) for i in range(self.tile_count)]
+
+    @property
     def form(self) -> str:
         f = int(L.lib().ptyc_get_form(self._ctx))
         return {L.PTYC_FORM_BATCH: "batch", L.PTYC_FORM_PERSISTENT: "persistent",
