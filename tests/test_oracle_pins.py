@@ -374,6 +374,29 @@ def test_strict_sweep_beta_and_alpha():
     np.testing.assert_array_equal(O0, wl.object0)
 
 
+def test_coloured_sweep_alpha_scales_the_object_step():
+    """In a coloured batch with beta = 0 the object step is linear in alpha
+    (each window's step depends only on its own pre-update values and the
+    batch's probe): alpha = 0 keeps the object, and the step at alpha = 0.4
+    is 0.4 times the step at alpha = 1."""
+    wl = _tiny_problem(noise=True)
+    idx = []
+    for j in range(wl.count):
+        if all(not oracle.windows_overlap(wl.positions[j], wl.positions[k], wl.n) for k in idx):
+            idx.append(j)
+    assert len(idx) >= 2
+    off = [0, len(idx)]
+    O0, P0 = wl.object0, wl.probe0
+    O1, P1, _, _ = oracle.sweep_coloured(O0, P0, wl.positions, wl.intensities, idx, off, alpha=1.0, beta=0.0)
+    Oa, Pa, _, _ = oracle.sweep_coloured(O0, P0, wl.positions, wl.intensities, idx, off, alpha=0.4, beta=0.0)
+    Oz, _, _, _ = oracle.sweep_coloured(O0, P0, wl.positions, wl.intensities, idx, off, alpha=0.0, beta=0.0)
+    np.testing.assert_array_equal(Oz, O0)
+    np.testing.assert_array_equal(P1, P0)
+    step1 = O1 - O0
+    assert np.max(np.abs(step1)) > 1e-3
+    np.testing.assert_allclose(Oa - O0, 0.4 * step1, rtol=0, atol=1e-13 * np.max(np.abs(step1)) + 1e-15)
+
+
 # ------------------------------------------------------------- subset-parallel scheme
 
 def test_parallel_one_subset_is_plain_reconstruction():
