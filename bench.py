@@ -303,9 +303,14 @@ def cpu_baseline(cfg_id, budget_s):
         done += len(idx)
         b += 1
     dt = time.perf_counter() - t0
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
     return dict(value=done / dt, unit="position updates/s", cores=1, kind="oracle",
                 sample=f"FP64 numpy oracle, coloured batches 0..{b - 1} of one sweep "
-                       f"({done} of {wl.count} position updates, {dt:.1f} s, single thread)")
+                       f"({done} of {wl.count} position updates, {dt:.1f} s, single thread)",
+                host_cpus={"cpu_count": os.cpu_count(), "affinity": affinity})
 
 
 def main():
