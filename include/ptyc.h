@@ -233,8 +233,11 @@ int ptyc_get_form(const ptyc_ctx* ctx);
  * several ways (ptyc_tile_count variants at the context's pattern size,
  * variant 0 the default); every variant produces the same object and probe
  * bit for bit and they differ only in speed.  ptyc_tune times each variant
- * on `reps` runs of one sweep over the loaded positions, each from the same
- * state with the same schedule, keeps the fastest, and restores the object,
+ * on `reps` runs of one sweep over the loaded positions (each from the same
+ * state with the same schedule; a variant's time is its best run), switches
+ * to the fastest if it beats the current variant by at least 2 % (else
+ * keeps the current one, so that noise does not flip the choice), and
+ * restores the object,
  * the probe and the sweep counter, so tuning leaves the reconstruction as it
  * was.  tile_out (nullable) receives the choice; ms_out (nullable,
  * PTYC_TILE_MAX entries) each variant's best sweep time in milliseconds (0

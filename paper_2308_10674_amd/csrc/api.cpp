@@ -446,6 +446,8 @@ int ptyc_set_tile(ptyc_ctx* c, int tile) {
 
 int ptyc_get_tile(const ptyc_ctx* c) { return c ? c->tile : -1; }
 
+constexpr double kTuneMargin = 0.02;   // a variant must be 2 % faster to replace the current one
+
 int ptyc_tune(ptyc_ctx* c, int32_t reps, int32_t* tile_out, double* ms_out) {
     int rc = usable(c);
     if (rc) return rc;
@@ -477,6 +479,7 @@ int ptyc_tune(ptyc_ctx* c, int32_t reps, int32_t* tile_out, double* ms_out) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = tile0;
     double best_ms = 0.0;
+    std::vector<double> times((size_t)nv, 0.0);
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he != hipSuccess) rc = hip_fail(c, he, "hipEventCreate");
@@ -496,10 +499,19 @@ int ptyc_tune(ptyc_ctx* c, int32_t reps, int32_t* tile_out, double* ms_out) {
         }
         if (rc != PTYC_OK) break;
         if (ms_out && v < PTYC_TILE_MAX) ms_out[v] = vbest;
-        if (v == 0 || vbest < best_ms) {
-            best_ms = vbest;
-            best = v;
-        }
+        times[(size_t)v] = vbest;
+    }
+    if (rc == PTYC_OK) {
+        // switch only for a clear gain: the variants are often within the
+        // noise of one another, and a choice that flips from call to call
+        // helps nobody
+        best = tile0;
+        best_ms = times[(size_t)tile0];
+        for (int v = 0; v < nv; ++v)
+            if (times[(size_t)v] < best_ms * (1.0 - kTuneMargin)) {
+                best = v;
+                best_ms = times[(size_t)v];
+            }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
