@@ -326,8 +326,9 @@ def main():
                     help="batch: three launches per batch; persistent: one cooperative kernel per sweep; "
                          "graph: one HIP graph replay per sweep")
     ap.add_argument("--no-forms", action="store_true", help="skip timing the other launch forms")
-    ap.add_argument("--tile", type=int, default=None,
-                    help="tile variant of the per-batch kernels (default: let ptyc_tune choose)")
+    ap.add_argument("--tile", default=None,
+                    help="tile variants of the per-batch kernels, 'A' or 'A,B' for the 128 px and the 256 px "
+                         "workload (default: let ptyc_tune choose)")
     ap.add_argument("--no-256", action="store_true", help="skip the 256 px workload")
     ap.add_argument("--steps-256", type=int, default=3)
     ap.add_argument("--no-multi", action="store_true", help="skip the 16 independent scans advanced together")
@@ -357,7 +358,11 @@ def main():
               "across GPUs, so --gpus must be 1.", file=sys.stderr)
         sys.exit(2)
 
-    r = run_gpu(1, args.steps, args.warmup, args.form, tile=args.tile)
+    tiles = [None, None]
+    if args.tile is not None:
+        parts = [int(x) for x in str(args.tile).split(",")]
+        tiles = [parts[0], parts[-1]]
+    r = run_gpu(1, args.steps, args.warmup, args.form, tile=tiles[0])
     wl = r["wl"]
     out = {
         "metric": "ePIE position updates/sec at 128^2 and 256^2 patterns; % HBM roofline",
@@ -395,7 +400,7 @@ def main():
     if not args.no_forms:
         out["forms"] = run_forms(wl, args.steps)
     if not args.no_256:
-        r2 = run_gpu(2, args.steps_256, 1, args.form, tile=args.tile)
+        r2 = run_gpu(2, args.steps_256, 1, args.form, tile=tiles[1])
         out["n256"] = {
             "value": round(r2["rate"], 1), "unit": "position updates/s",
             "ms_per_step": round(r2["ms"] / args.steps_256, 3), "steps": args.steps_256,
