@@ -47,6 +47,20 @@ def test_variants_give_the_same_bytes(which):
     progress(f"tile variants {which}: {ref.tile_count} agree")
 
 
+def test_graph_is_rebuilt_when_the_tile_changes():
+    """A tile change between sweeps in the graph form rebuilds the graph; the
+    bytes stay those of the batch form."""
+    wl = sim.make_config(1, n_positions=600)
+    g = engine_for(wl, form="graph")
+    b = engine_for(wl)
+    for v in (0, 2, 1, 0):
+        g.tile = v
+        g.sweep(1)
+        b.sweep(1)
+        np.testing.assert_array_equal(g.get_object(), b.get_object(), err_msg=f"variant {v}")
+        np.testing.assert_array_equal(g.get_probe(), b.get_probe(), err_msg=f"variant {v}")
+
+
 def test_tune_leaves_the_reconstruction_unchanged():
     wl = sim.make_config(1, n_positions=600)
     a = engine_for(wl)
