@@ -208,6 +208,7 @@ def roofline_of(r):
         "bound": "hbm", "kernel": f"{name}<{n}>", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": None if tr is None else int(tr["bytes_per_launch"]),
+        "traffic_GBps": None if tr is None else round(tr["bytes_per_launch"] / avg_s / 1e9, 2),
         "algorithmic_bytes_per_launch": round(per_launch_bytes),
         "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
         "kernel_times_ms": {k: round(v[0], 3) for k, v in r["kernels"].items()},
