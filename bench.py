@@ -215,6 +215,29 @@ def roofline_of(r):
     }
 
 
+def copy_bandwidth(reps=5):
+    """Measured stream-copy rate of this GPU (x -> -x over 512 MiB, read plus
+    written bytes over the best of `reps` event-timed launches), reported
+    beside the nominal HBM peak."""
+    import torch
+
+    x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.neg(x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    gbs = 2 * x.numel() * 4 / (best / 1e3) / 1e9
+    del x, y
+    return round(gbs, 1)
+
+
 def run_multi(steps, warmup, n_scans=16):
     """Sixteen independent scans of uneven size (pattern sizes 64/128/256,
     500-5000 positions, raster or spiral): per-scan sweeps one after the
@@ -423,7 +446,7 @@ def main():
             "batches_per_sweep": r["batches"], "mean_batch": round(r["mean_batch"], 2),
             "max_batch": r["max_batch"], "tile": r["tile"], "tile_ms_per_sweep": r["tile_ms"],
         },
-        "roofline": roofline_of(r),
+        "roofline": dict(roofline_of(r), copy_GBps=copy_bandwidth()),
         "path": {
             "achieved": round(r["achieved_gbs"], 2), "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 5),
             "bytes_per_update": algorithmic_bytes(wl.n),

@@ -47,7 +47,7 @@ struct ptyc_ctx {
     int64_t slots = 0;
     DevBuf pmax_part;                // two halves of max_probe_blocks floats (see pmax_cur)
     int pmax_cur = 0;                // the half holding the current probe's partial maxima
-    DevBuf order;                    // int64 [order_cap]
+    DevBuf order;                    // OrderEntry [order_cap]
     DevBuf offs;                     // int64 batch offsets of the persistent form
     DevBuf err_part, err_dev;
     DevBuf bad;                      // int flag for ingest validation
@@ -61,7 +61,7 @@ struct ptyc_ctx {
     std::vector<int32_t> h_pos;      // 2 per position
     Colouring* colouring = nullptr;
     int64_t sweeps_done = 0;
-    int64_t* pinned_order = nullptr; // pinned upload buffer (orders, then offsets)
+    int64_t* pinned_order = nullptr; // pinned upload buffer (order entries, then offsets)
     size_t pinned_bytes = 0;
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
@@ -214,7 +214,7 @@ BatchArgs base_args(ptyc_ctx* c) {
     a.tw = (const cf*)c->tw.p;
     a.sqrt_i = (const float*)c->sqrt_i.p;
     a.pos = (const int2*)c->pos.p;
-    a.order = (const int64_t*)c->order.p;
+    a.order = (const OrderEntry*)c->order.p;
     a.scratch = (cf*)c->scratch.p;
     a.winmax = (float*)c->winmax.p;
     a.pmax_in = pmax_half(c, c->pmax_cur);
@@ -748,6 +748,14 @@ int plan_sweeps(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t ord
     return PTYC_OK;
 }
 
+// The device form of an order: each position index with its window corner.
+void to_entries(const ptyc_ctx* c, const int64_t* idx, int64_t n, OrderEntry* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = idx[i];
+        out[i] = OrderEntry{c->h_pos[(size_t)(2 * j)], c->h_pos[(size_t)(2 * j + 1)], j};
+    }
+}
+
 // Size the work buffers for a plan, upload its orders and offsets, refresh
 // the probe maxima in the layout of `form`.
 int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
@@ -758,7 +766,7 @@ int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
         if ((rc = ensure(c, c->winmax, (size_t)p.max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
         c->slots = p.max_b;
     }
-    const size_t obytes = (size_t)n_sweeps * p.olen * sizeof(int64_t);
+    const size_t obytes = (size_t)n_sweeps * p.olen * sizeof(OrderEntry);
     const size_t fbytes = (size_t)n_sweeps * (p.nb + 1) * sizeof(int64_t);
     if (c->upload_pending) {
         HIPCHK(c, hipEventSynchronize(c->upload_done));
@@ -779,9 +787,10 @@ int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
         }
         c->pinned_bytes = obytes + fbytes;
     }
-    int64_t* pin_off = c->pinned_order + (size_t)n_sweeps * p.olen;
+    OrderEntry* pin_ent = (OrderEntry*)c->pinned_order;
+    int64_t* pin_off = (int64_t*)(pin_ent + (size_t)n_sweeps * p.olen);
     for (int s = 0; s < n_sweeps; ++s) {
-        std::memcpy(c->pinned_order + (size_t)s * p.olen, p.orders[(size_t)s].data(), (size_t)p.olen * sizeof(int64_t));
+        to_entries(c, p.orders[(size_t)s].data(), p.olen, pin_ent + (size_t)s * p.olen);
         std::memcpy(pin_off + (size_t)s * (p.nb + 1), p.offs[(size_t)s].data(), (size_t)(p.nb + 1) * sizeof(int64_t));
     }
     HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, obytes, hipMemcpyHostToDevice, c->stream));
@@ -798,7 +807,7 @@ int stage_plan(ptyc_ctx* c, const Plan& p, int32_t n_sweeps, int form) {
 // the error-metric reduction of sweep s of a plan whose column stage wrote
 // gc partials per position
 int launch_sweep_error(ptyc_ctx* c, const Plan& p, int s, int gc) {
-    const int64_t* ord = (const int64_t*)c->order.p + (size_t)s * p.olen;
+    const OrderEntry* ord = (const OrderEntry*)c->order.p + (size_t)s * p.olen;
     HIPCHK(c, launch_err_reduce((const double*)c->err_part.p, p.olen * gc, ord, p.olen, (const double*)c->sum_i.p,
                                 (double*)c->err_dev.p + s, c->stream));
     return PTYC_OK;
@@ -817,12 +826,12 @@ bool same_key(const BatchArgs& x, const BatchArgs& y) {
 // the sweep's order and offsets into the graph's fixed buffers, replay
 int graph_sweep(ptyc_ctx* c, const Plan& p, int s) {
     int rc;
-    if ((rc = ensure(c, c->gorder, (size_t)p.olen * sizeof(int64_t))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->gorder, (size_t)p.olen * sizeof(OrderEntry))) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->goffs, (size_t)(p.nb + 1) * sizeof(int64_t))) != PTYC_OK) return rc;
     // the graph's first node reads the maxima from half 0
     if (c->pmax_cur != 0 && (rc = refresh_probe_max(c)) != PTYC_OK) return rc;
     BatchArgs a = base_args(c);
-    a.order = (const int64_t*)c->gorder.p;
+    a.order = (const OrderEntry*)c->gorder.p;
     a.boffs = (const int64_t*)c->goffs.p;
     if (!c->gexec || c->g_nb != p.nb || c->g_maxb < p.max_b || c->g_tile != c->tile || !same_key(a, c->gkey)) {
         if (c->gexec) {
@@ -843,8 +852,8 @@ int graph_sweep(ptyc_ctx* c, const Plan& p, int s) {
         c->g_maxb = p.max_b;
         c->g_tile = c->tile;
     }
-    HIPCHK(c, hipMemcpyAsync(c->gorder.p, (const int64_t*)c->order.p + (size_t)s * p.olen,
-                             (size_t)p.olen * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->gorder.p, (const OrderEntry*)c->order.p + (size_t)s * p.olen,
+                             (size_t)p.olen * sizeof(OrderEntry), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->goffs.p, (const int64_t*)c->offs.p + (size_t)s * (p.nb + 1),
                              (size_t)(p.nb + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
     size_t e0 = 0;
@@ -883,7 +892,7 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
     const int64_t olen = p.olen, nb = p.nb;
     for (int s = 0; s < n_sweeps; ++s) {
         BatchArgs a = base_args(c);
-        a.order = (const int64_t*)c->order.p + (size_t)s * olen;
+        a.order = (const OrderEntry*)c->order.p + (size_t)s * olen;
         if (c->form == kFormPersistent) {
             SweepCtl ctl{};
             ctl.offs = (const int64_t*)c->offs.p + (size_t)s * (nb + 1);
@@ -989,7 +998,7 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
                 const int64_t b = k % p.nb;
                 BatchArgs a = base_args(c);
                 c->pmax_cur ^= 1;   // this entry's inverse stage writes the other half
-                a.order = (const int64_t*)c->order.p + (size_t)s * p.olen;
+                a.order = (const OrderEntry*)c->order.p + (size_t)s * p.olen;
                 a.off = p.offs[(size_t)s][(size_t)b];
                 a.bsize = (int)(p.offs[(size_t)s][(size_t)b + 1] - a.off);
                 tab.push_back(a);
@@ -1143,7 +1152,9 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
         if ((rc = ensure(c, c->winmax, (size_t)max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
         c->slots = max_b;
     }
-    const size_t obytes = (size_t)count * sizeof(int64_t);
+    std::vector<OrderEntry> ents((size_t)count);
+    to_entries(c, order.data(), count, ents.data());
+    const size_t obytes = (size_t)count * sizeof(OrderEntry);
     if (c->upload_pending) {
         HIPCHK(c, hipEventSynchronize(c->upload_done));
         c->upload_pending = false;
@@ -1151,7 +1162,7 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
     if ((rc = ensure(c, c->order, obytes)) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->err_part, (size_t)count * c->sb.col_blocks * sizeof(double))) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->err_dev, sizeof(double))) != PTYC_OK) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->order.p, order.data(), obytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->order.p, ents.data(), obytes, hipMemcpyHostToDevice, c->stream));
     BatchArgs a = base_args(c);
     a.obj = (cf*)obj;
     a.probe = (cf*)probe;

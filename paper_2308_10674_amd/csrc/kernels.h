@@ -8,6 +8,13 @@
 
 namespace ptyc {
 
+// One entry of a sweep's order on the device: the position's window corner
+// stored beside its index, so a stage reaches both with a single load.
+struct OrderEntry {
+    int32_t row, col;         // window corner (top-left) in the object
+    int64_t j;                // position index (row of sqrt_i, sum_i)
+};
+
 // Everything one batch of positions needs.  Device pointers only.
 struct BatchArgs {
     cf* obj;                  // [h][w] object, updated in place
@@ -16,7 +23,7 @@ struct BatchArgs {
     const cf* tw;             // [n] exp(-2 pi i m / n)
     const float* sqrt_i;      // [cap][n][n] measured moduli
     const int2* pos;          // [cap] window corners (row, col)
-    const int64_t* order;     // this sweep's position order
+    const OrderEntry* order;  // this sweep's order
     int64_t off;              // first order entry of this batch
     int bsize;                // positions in this batch
     cf* scratch;              // [slots][n][n] spectrum exchange between stages
@@ -33,7 +40,7 @@ struct BatchArgs {
     cf* gprobe;               // amplitude-loss gradient w.r.t. the probe (accumulated)
     float gscale;             // upstream scale of the gradient
     const unsigned char* mask;  // [n][n] 1 = measured detector pixel; nullptr: all measured
-    const int64_t* boffs;     // if set: off and bsize are read from boffs[batch], boffs[batch + 1]
+    const int64_t* boffs;     // graph nodes: off and bsize are read from boffs[batch], boffs[batch + 1]
     int batch;
     int n;                    // pattern size (read by the mixed-size kernels)
 };
@@ -115,7 +122,7 @@ hipError_t launch_mean(void* const* ptrs, int k, int64_t count_c64, hipStream_t 
 hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hipStream_t s);
 hipError_t launch_ingest(int n, const float* src, float* sqrt_i_dst, double* sum_i_dst,
                          int64_t count, const IngestSpec& spec, int* bad_flag, hipStream_t s);
-hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const int64_t* order,
+hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const OrderEntry* order,
                              int64_t order_len, const double* sum_i, double* err_out,
                              hipStream_t s);
 

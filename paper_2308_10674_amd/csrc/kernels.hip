@@ -207,6 +207,18 @@ template <int N, int R_ = ITile<N>::R, int S_ = ITile<N>::S> struct InvG {
 template <int N> constexpr int kWinParts = N * Fact<N>::N2 / kWave;
 template <int N> constexpr int kProbeParts = N * N / kWave;
 
+// Stores of the bulk data that the next kernel reads on other XCDs (the
+// spectrum exchange and the object window): written through this XCD's L2
+// (an agent-scope relaxed store, i.e. a plain store with the agent
+// coherence bit), so no dirty lines are left for the write-back at the end
+// of the kernel.  The stored value is unchanged.
+__device__ __forceinline__ void store_through(cf* p, cf v) {
+    unsigned long long bits;
+    __builtin_memcpy(&bits, &v, sizeof(bits));
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), bits, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- stage 1
 // psi = P * S_j O for rows rb*RB .. rb*RB+RB-1 of slot `slot`, 1D FFT of
 // each row, spectrum rows to scratch; partial max |S_j O|^2 to winmax, one
@@ -215,11 +227,10 @@ template <int N, int RB>
 __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds,
                                                float* red) {
     using g = RowG<N, RB>;
-    const int64_t j = a.order[a.off + slot];
-    const int2 p0 = a.pos[j];
+    const OrderEntry e = a.order[a.off + slot];
     const int t = threadIdx.x % g::T, rl = threadIdx.x / g::T;
     const int r = rb * RB + rl;
-    const cf* orow = a.obj + (size_t)(p0.x + r) * a.w + p0.y;
+    const cf* orow = a.obj + (size_t)(e.row + r) * a.w + e.col;
     const cf* prow = a.probe + (size_t)r * N;
     cf v[g::N1];
     float m = 0.f;
@@ -236,7 +247,7 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
     passB_from_lds<N, -1, 1>(v, z, t);
     cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
 #pragma unroll
-    for (int i = 0; i < g::N1; ++i) srow[Fact<N>::out(t, i)] = v[i];
+    for (int i = 0; i < g::N1; ++i) store_through(&srow[Fact<N>::out(t, i)], v[i]);
     m = wave_max(m);
     if (threadIdx.x % kWave == 0) a.winmax[slot * kWinParts<N> + rb * (g::NT / kWave) + threadIdx.x / kWave] = m;
 }
@@ -248,7 +259,7 @@ template <int N, int CB, int MODE = kModeEpie>
 __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds,
                                            double* red) {
     using g = ColG<N, CB>;
-    const int64_t j = a.order[a.off + slot];
+    const int64_t j = a.order[a.off + slot].j;
     const int cl = threadIdx.x % CB, t = threadIdx.x / CB;
     const int c = cb * CB + cl;
     cf* base = a.scratch + (size_t)slot * N * N + c;
@@ -298,7 +309,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
         __syncthreads();
         passAinv_from_lds<N, +1>(v, z, t);
 #pragma unroll
-        for (int n1 = 0; n1 < g::N1; ++n1) base[(size_t)(g::N2 * n1 + t) * N] = v[n1];
+        for (int n1 = 0; n1 < g::N1; ++n1) store_through(&base[(size_t)(g::N2 * n1 + t) * N], v[n1]);
     }
     const double tot = block_sum<g::NT>((double)e, red);
     if (threadIdx.x == 0) a.err_part[(a.off + slot) * g::GC + cb] = tot;
@@ -351,9 +362,9 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             cf* orow = nullptr;
             float om = 1.f;
             if (act) {
-                const int2 p0 = a.pos[a.order[a.off + slot]];
+                const OrderEntry e = a.order[a.off + slot];
                 const cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
-                orow = a.obj + (size_t)(p0.x + r) * a.w + p0.y;
+                orow = a.obj + (size_t)(e.row + r) * a.w + e.col;
 #pragma unroll
                 for (int i = 0; i < g::N1; ++i) v[i] = srow[Fact<N>::out(t, i)];
 #pragma unroll
@@ -390,13 +401,13 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     const int col = g::N2 * n1 + t;
                     const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
-                    orow[col] = o[n1] + ostep * cmulc(p[n1], delta);
+                    store_through(&orow[col], o[n1] + ostep * cmulc(p[n1], delta));
                     drow[col] = pstep * cmulc(o[n1], delta);
                 }
             } else if (act) {
                 // v = F^H g_Psi = dL/dpsi: dL/dO on the window += conj(P) g, dL/dP += conj(S_j O) g
-                const int2 p0 = a.pos[a.order[a.off + slot]];
-                cf* grow = a.gobj + (size_t)(p0.x + r) * a.w + p0.y;
+                const OrderEntry e = a.order[a.off + slot];
+                cf* grow = a.gobj + (size_t)(e.row + r) * a.w + e.col;
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     const int col = g::N2 * n1 + t;
@@ -454,35 +465,39 @@ __device__ __forceinline__ BatchArgs resolved(const BatchArgs& a) {
     return r;
 }
 
-template <int N, int RB = Tile<N>::RB>
+// DEV: the batch's extent comes from device memory (graph nodes; their grids
+// cover the largest batch, so surplus workgroups return at once).  Without
+// it the extent is an argument and every caller sizes the grid to the batch
+// exactly, so the kernel starts its loads without the branch and the check.
+template <int N, int RB = Tile<N>::RB, bool DEV = false>
 __global__ __launch_bounds__((RowG<N, RB>::NT)) void k_rows_fwd(BatchArgs a) {
     using g = RowG<N, RB>;
     __shared__ cf lds[RB * Lds<N>::LINE];
     __shared__ float red[g::NT / kWave];
-    const BatchArgs b = resolved(a);
+    const BatchArgs b = DEV ? resolved(a) : a;
     const int slot = blockIdx.x / g::G;
-    if (slot >= b.bsize) return;   // a grid sized for a larger batch (whole workgroup)
+    if (DEV && slot >= b.bsize) return;   // a grid sized for a larger batch (whole workgroup)
     stage_rows_fwd<N, RB>(b, slot, blockIdx.x % g::G, lds, red);
 }
 
-template <int N, int CB = Tile<N>::CB>
+template <int N, int CB = Tile<N>::CB, bool DEV = false>
 __global__ __launch_bounds__((ColG<N, CB>::NT)) void k_cols(BatchArgs a) {
     using g = ColG<N, CB>;
     __shared__ cf lds[CB * Lds<N>::LINE];
     __shared__ double red[g::NT / kWave];
-    const BatchArgs b = resolved(a);
+    const BatchArgs b = DEV ? resolved(a) : a;
     const int slot = blockIdx.x / g::GC;
-    if (slot >= b.bsize) return;
+    if (DEV && slot >= b.bsize) return;
     stage_cols<N, CB>(b, slot, blockIdx.x % g::GC, lds, red);
 }
 
-template <int N, int R = ITile<N>::R, int S = ITile<N>::S>
+template <int N, int R = ITile<N>::R, int S = ITile<N>::S, bool DEV = false>
 __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     using g = InvG<N, R, S>;
     __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
     __shared__ cf dl[g::S * g::R * N];
     __shared__ float red[g::NT / kWave];
-    stage_rows_inv<N, g::R, g::S>(resolved(a), blockIdx.x, lds, dl, red);
+    stage_rows_inv<N, g::R, g::S>(DEV ? resolved(a) : a, blockIdx.x, lds, dl, red);
 }
 
 // Several reconstructions at once: workgroup b belongs to descriptor i with
@@ -777,12 +792,12 @@ __global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ src, f
 
 // ---------------------------------------------------------------- error
 __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int64_t n_part,
-                                                    const int64_t* order, int64_t order_len,
+                                                    const OrderEntry* order, int64_t order_len,
                                                     const double* sum_i, double* out, int raw) {
     __shared__ double red[256 / kWave];
     double num = 0.0, den = 0.0;
     for (int64_t i = threadIdx.x; i < n_part; i += 256) num += err_part[i];
-    for (int64_t i = threadIdx.x; i < order_len; i += 256) den += sum_i[order[i]];
+    for (int64_t i = threadIdx.x; i < order_len; i += 256) den += sum_i[order[i].j];
     num = block_sum<256>(num, red);
     den = block_sum<256>(den, red);
     if (threadIdx.x == 0) *out = raw ? num : (den > 0.0 ? num / den : 0.0);
@@ -875,10 +890,11 @@ hipError_t graph_n(const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {
         }
         ab.off = 0;
         ab.bsize = 0;
-        e = add(reinterpret_cast<const void*>(&k_rows_fwd<N, tv.rb>), rg::G * max_b, rg::NT, &ab);
-        if (e == hipSuccess) e = add(reinterpret_cast<const void*>(&k_cols<N, tv.cb>), cg::GC * max_b, cg::NT, &ab);
+        e = add(reinterpret_cast<const void*>(&k_rows_fwd<N, tv.rb, true>), rg::G * max_b, rg::NT, &ab);
         if (e == hipSuccess)
-            e = add(reinterpret_cast<const void*>(&k_rows_inv<N, tv.r, tv.s>), ig::GI, ig::NT, &ab);
+            e = add(reinterpret_cast<const void*>(&k_cols<N, tv.cb, true>), cg::GC * max_b, cg::NT, &ab);
+        if (e == hipSuccess)
+            e = add(reinterpret_cast<const void*>(&k_rows_inv<N, tv.r, tv.s, true>), ig::GI, ig::NT, &ab);
     }
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g);
@@ -1079,7 +1095,7 @@ hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s) {
 }
 
 hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, s, part, n_part, (const int64_t*)nullptr,
+    hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, s, part, n_part, (const OrderEntry*)nullptr,
                        (int64_t)0, (const double*)nullptr, out, 1);
     return hipGetLastError();
 }
@@ -1090,7 +1106,7 @@ hipError_t launch_ingest(int n, const float* src, float* dst, double* sum_i, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const int64_t* order,
+hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const OrderEntry* order,
                              int64_t order_len, const double* sum_i, double* err_out,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, s, err_part, n_part, order, order_len,
