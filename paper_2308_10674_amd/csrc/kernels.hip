@@ -32,25 +32,65 @@ namespace {
 
 constexpr int kWave = 64;
 
-__device__ inline float wave_max(float v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
+// Cross-lane reductions.  Inside a row of 16 lanes they use DPP operand
+// controls (a VALU modifier, no trip through the LDS unit): the quad
+// permutations [1,0,3,2] and [2,3,0,1], then the half-row and the row
+// mirrors.  Each step combines a lane with a partner holding the same
+// number of inputs, so after the four steps every lane of the row holds the
+// row's result, computed the same way in every lane.  The four rows are
+// then combined through readlane (uniform results) in a fixed order.
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane_of(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double lane_of(double v, int lane) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// max over aligned groups of G consecutive lanes (G a power of two, at most
-// a wave); every lane of a group gets the group's result
+// max over aligned groups of G lanes (G = 2, 4, 8, 16 or 32); every lane of
+// a group gets the group's result
 template <int G>
 __device__ inline float group_max(float v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
+    v = fmaxf(v, dpp<kDppQuadXor1>(v));
+    if constexpr (G >= 4) v = fmaxf(v, dpp<kDppQuadXor2>(v));
+    if constexpr (G >= 8) v = fmaxf(v, dpp<kDppRowHalfMirror>(v));
+    if constexpr (G >= 16) v = fmaxf(v, dpp<kDppRowMirror>(v));
+    if constexpr (G == 32) v = fmaxf(v, __shfl_xor(v, 16, kWave));
     return v;
+}
+
+// max over the wave (uniform result)
+__device__ inline float wave_max(float v) {
+    v = group_max<16>(v);
+    return fmaxf(fmaxf(lane_of(v, 0), lane_of(v, 16)), fmaxf(lane_of(v, 32), lane_of(v, 48)));
+}
+
+// sum over the wave in a fixed order (uniform result)
+__device__ inline double wave_sum(double v) {
+    v += dpp<kDppQuadXor1>(v);
+    v += dpp<kDppQuadXor2>(v);
+    v += dpp<kDppRowHalfMirror>(v);
+    v += dpp<kDppRowMirror>(v);
+    return (lane_of(v, 0) + lane_of(v, 16)) + (lane_of(v, 32) + lane_of(v, 48));
 }
 
 // block-wide max; every thread gets the result
