@@ -181,19 +181,53 @@ struct Lds {
     __host__ __device__ static inline int at(int k1, int n2) { return k1 * (N2 + 1) + n2; }
 };
 
-// Pass A of a forward (DIR=-1) transform.  In: v[n1] = x[N2 n1 + t].
-// Out: Z[k1][t] = W_N^(t k1) * sum_n1 x[N2 n1 + t] W_N1^(n1 k1).
-// tw[m] = exp(-2 pi i m / N), m < N.
+// The W_N twiddles one thread applies, taken from tw[m] = exp(-2 pi i m / N),
+// m < N, into registers ahead of the pass (so a kernel can issue these
+// loads before its other memory traffic): N1 per thread for pass A
+// (w[k1] = W_N^(DIR t k1)) and N1 for the inverse of pass B (w[i] = the
+// factor of the i-th element the thread writes).
 template <int N, int DIR>
-__host__ __device__ inline void passA_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+__host__ __device__ inline void twiddles_a(cf* w, int t, const cf* __restrict__ tw) {
+#pragma unroll
+    for (int k1 = 0; k1 < Fact<N>::N1; ++k1) {
+        cf x = tw[t * k1];
+        if (DIR > 0) x.y = -x.y;
+        w[k1] = x;
+    }
+}
+
+template <int N, int DIR>
+__host__ __device__ inline void twiddles_binv(cf* w, int t, const cf* __restrict__ tw) {
+    constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
+    if constexpr (Fact<N>::L == 1) {
+#pragma unroll
+        for (int m = 0; m < N1 / N2; ++m)
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) {
+                cf x = tw[n2 * (t + N2 * m)];
+                if (DIR > 0) x.y = -x.y;
+                w[m * N2 + n2] = x;
+            }
+    } else {
+        const int k1 = t >> 1, h = t & 1;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            cf x = tw[(2 * m + h) * k1];
+            if (DIR > 0) x.y = -x.y;
+            w[m] = x;
+        }
+    }
+}
+
+// Pass A of a transform in direction DIR.  In: v[n1] = x[N2 n1 + t].
+// Out: Z[k1][t] = W_N^(DIR t k1) * sum_n1 x[N2 n1 + t] W_N1^(DIR n1 k1);
+// w = twiddles_a<N, DIR>.
+template <int N, int DIR>
+__host__ __device__ inline void passA_to_lds(cf* v, cf* z, int t, const cf* w) {
     constexpr int N1 = Fact<N>::N1;
     dft<N1, DIR>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-        cf w = tw[t * k1];
-        if (DIR > 0) w.y = -w.y;
-        z[Lds<N>::at(k1, t)] = (k1 == 0) ? v[k1] : cmul(v[k1], w);
-    }
+    for (int k1 = 0; k1 < N1; ++k1) z[Lds<N>::at(k1, t)] = (k1 == 0) ? v[k1] : cmul(v[k1], w[k1]);
 }
 
 // Pass B with L = 1.  Thread t handles k1 = t + N2 m, m < N1/N2.
@@ -215,9 +249,10 @@ __host__ __device__ inline void passB1_from_lds(cf* v, const cf* z, int t) {
 
 // Inverse of pass B with L = 1: from v[m N2 + k2] = X[(t + N2 m) + N1 k2]
 // to Z[k1][n2] = W_N^(DIR n2 k1) * sum_k2 X[k1 + N1 k2] W_N2^(DIR n2 k2) for
-// the transform direction DIR (the conjugate of the forward direction).
+// the transform direction DIR (the conjugate of the forward direction);
+// w = twiddles_binv<N, DIR>.
 template <int N, int DIR>
-__host__ __device__ inline void passB1inv_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+__host__ __device__ inline void passB1inv_to_lds(cf* v, cf* z, int t, const cf* w) {
     constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2;
 #pragma unroll
     for (int m = 0; m < N1 / N2; ++m) {
@@ -227,11 +262,7 @@ __host__ __device__ inline void passB1inv_to_lds(cf* v, cf* z, int t, const cf* 
         for (int k2 = 0; k2 < N2; ++k2) u[k2] = v[m * N2 + k2];
         dft<N2, DIR>(u);
 #pragma unroll
-        for (int n2 = 0; n2 < N2; ++n2) {
-            cf w = tw[n2 * k1];
-            if (DIR > 0) w.y = -w.y;
-            z[Lds<N>::at(k1, n2)] = cmul(u[n2], w);
-        }
+        for (int n2 = 0; n2 < N2; ++n2) z[Lds<N>::at(k1, n2)] = cmul(u[n2], w[m * N2 + n2]);
     }
 }
 
@@ -276,19 +307,14 @@ __host__ __device__ inline void passB2inv_combine(cf* v, const cf* p, int t) {
 }
 
 // ... then each lane alone: the length-N1 DFT gives Z'[k1][2 m + h], which
-// is twiddled by W_N^(DIR n2 k1) into the LDS line.
+// is twiddled by W_N^(DIR n2 k1) into the LDS line (w = twiddles_binv).
 template <int N, int DIR>
-__host__ __device__ inline void passB2inv_local_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+__host__ __device__ inline void passB2inv_local_to_lds(cf* v, cf* z, int t, const cf* w) {
     constexpr int N1 = Fact<N>::N1;
     const int k1 = t >> 1, h = t & 1;
     dft<N1, DIR>(v);
 #pragma unroll
-    for (int m = 0; m < N1; ++m) {
-        const int n2 = 2 * m + h;
-        cf w = tw[n2 * k1];
-        if (DIR > 0) w.y = -w.y;
-        z[Lds<N>::at(k1, n2)] = cmul(v[m], w);
-    }
+    for (int m = 0; m < N1; ++m) z[Lds<N>::at(k1, 2 * m + h)] = cmul(v[m], w[m]);
 }
 
 // Inverse of pass A: thread t = n2 reads Z[k1][t], k1 < N1, and ends with
@@ -324,15 +350,15 @@ __device__ inline void passB_from_lds(cf* v, const cf* z, int t) {
 }
 
 template <int N, int DIR, int XOR>
-__device__ inline void passBinv_to_lds(cf* v, cf* z, int t, const cf* __restrict__ tw) {
+__device__ inline void passBinv_to_lds(cf* v, cf* z, int t, const cf* w) {
     if constexpr (Fact<N>::L == 1) {
-        passB1inv_to_lds<N, DIR>(v, z, t, tw);
+        passB1inv_to_lds<N, DIR>(v, z, t, w);
     } else {
         cf p[Fact<N>::N1];
 #pragma unroll
         for (int i = 0; i < Fact<N>::N1; ++i) p[i] = lane_swap<XOR>(v[i]);
         passB2inv_combine<N, DIR>(v, p, t);
-        passB2inv_local_to_lds<N, DIR>(v, z, t, tw);
+        passB2inv_local_to_lds<N, DIR>(v, z, t, w);
     }
 }
 

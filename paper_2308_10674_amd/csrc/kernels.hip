@@ -267,8 +267,10 @@ template <int N, int RB>
 __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds,
                                                float* red) {
     using g = RowG<N, RB>;
-    const OrderEntry e = a.order[a.off + slot];
     const int t = threadIdx.x % g::T, rl = threadIdx.x / g::T;
+    cf w[g::N1];
+    twiddles_a<N, -1>(w, t, a.tw);
+    const OrderEntry e = a.order[a.off + slot];
     const int r = rb * RB + rl;
     const cf* orow = a.obj + (size_t)(e.row + r) * a.w + e.col;
     const cf* prow = a.probe + (size_t)r * N;
@@ -282,7 +284,7 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
         v[n1] = cmul(prow[col], o);
     }
     cf* z = lds + rl * Lds<N>::LINE;
-    passA_to_lds<N, -1>(v, z, t, a.tw);
+    passA_to_lds<N, -1>(v, z, t, w);
     __syncthreads();
     passB_from_lds<N, -1, 1>(v, z, t);
     cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
@@ -299,8 +301,12 @@ template <int N, int CB, int MODE = kModeEpie>
 __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds,
                                            double* red) {
     using g = ColG<N, CB>;
-    const int64_t j = a.order[a.off + slot].j;
     const int cl = threadIdx.x % CB, t = threadIdx.x / CB;
+    // twiddles first: the first pass then waits for them and the spectrum
+    // only, not for sqrt(I) (loads complete in issue order)
+    cf wa[g::N1], wb[g::N1];
+    twiddles_a<N, -1>(wa, t, a.tw);
+    const int64_t j = a.order[a.off + slot].j;
     const int c = cb * CB + cl;
     cf* base = a.scratch + (size_t)slot * N * N + c;
     const float* ampb = a.sqrt_i + (size_t)j * N * N + c;
@@ -315,8 +321,9 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
         amp[i] = ampb[(size_t)row * N];
         valid[i] = a.mask == nullptr || a.mask[row * N + c] != 0;
     }
+    twiddles_binv<N, +1>(wb, t, a.tw);
     cf* z = lds + cl * Lds<N>::LINE;
-    passA_to_lds<N, -1>(v, z, t, a.tw);
+    passA_to_lds<N, -1>(v, z, t, wa);
     __syncthreads();
     passB_from_lds<N, -1, CB>(v, z, t);
     float e = 0.f;
@@ -345,7 +352,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
     }
     if (MODE != kModeLoss) {
         __syncthreads();
-        passBinv_to_lds<N, +1, CB>(v, z, t, a.tw);
+        passBinv_to_lds<N, +1, CB>(v, z, t, wb);
         __syncthreads();
         passAinv_from_lds<N, +1>(v, z, t);
 #pragma unroll
@@ -393,6 +400,10 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             pm = wave_max(pm);
             ostep = a.alpha / pm;
         }
+        // twiddles ahead of the slot loads: the transform then waits for
+        // them and the spectrum row only (loads complete in issue order)
+        cf wb[g::N1];
+        twiddles_binv<N, +1>(wb, t, a.tw);
         cf* z = lds + (sl * g::R + rl) * Lds<N>::LINE;
         cf* drow = dl + (sl * g::R + rl) * N;
         for (int g0 = 0; g0 < a.bsize; g0 += g::S) {
@@ -416,24 +427,30 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                     o[n1] = cf{0.f, 0.f};
                 }
             }
+            // max |S_j O|^2 from the forward stage's per-wave partials,
+            // loaded now and reduced by the slot's own threads after the
+            // transform, so the transform does not wait for these loads
+            // and the object row's (an idle slot reads slot 0's partials,
+            // which exist, and discards the result)
+            constexpr int GT = g::T * g::R;
+            constexpr int kWm = (kWinParts<N> + GT - 1) / GT;
+            float wpart[kWm];
+            const int ws = act ? slot : 0;
+#pragma unroll
+            for (int k = 0; k < kWm; ++k) {
+                const int i = k * GT + (int)(threadIdx.x % GT);
+                wpart[k] = MODE == kModeEpie && i < kWinParts<N> ? a.winmax[ws * kWinParts<N> + i] : 0.f;
+            }
+            passBinv_to_lds<N, +1, 1>(v, z, t, wb);
+            __syncthreads();
+            passAinv_from_lds<N, +1>(v, z, t);
             if (MODE == kModeEpie) {
-                // max |S_j O|^2 from the forward stage's per-wave partials,
-                // reduced by the slot's own threads (an idle slot reads
-                // slot 0's, which exists, and discards the result)
-                constexpr int GT = g::T * g::R;
-                const int ws = act ? slot : 0;
                 float wm = 0.f;
 #pragma unroll
-                for (int k = 0; k < (kWinParts<N> + GT - 1) / GT; ++k) {
-                    const int i = k * GT + (int)(threadIdx.x % GT);
-                    if (i < kWinParts<N>) wm = fmaxf(wm, a.winmax[ws * kWinParts<N> + i]);
-                }
+                for (int k = 0; k < kWm; ++k) wm = fmaxf(wm, wpart[k]);
                 wm = group_max<GT>(wm);
                 if (act) om = wm;
             }
-            passBinv_to_lds<N, +1, 1>(v, z, t, a.tw);
-            __syncthreads();
-            passAinv_from_lds<N, +1>(v, z, t);
             constexpr float inv = 1.0f / (float)(N * N);
             const float pstep = 1.f / om;
             if (act && MODE == kModeEpie) {

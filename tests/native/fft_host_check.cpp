@@ -61,7 +61,9 @@ static int check_line() {
     std::vector<std::vector<cf>> regs(N2, std::vector<cf>(N1));
     for (int t = 0; t < N2; ++t) {
         for (int n1 = 0; n1 < N1; ++n1) regs[t][n1] = x[N2 * n1 + t];
-        passA_to_lds<N, -1>(regs[t].data(), z.data(), t, tw.data());
+        cf w[N1];
+        twiddles_a<N, -1>(w, t, tw.data());
+        passA_to_lds<N, -1>(regs[t].data(), z.data(), t, w);
     }
     if constexpr (Fact<N>::L == 1) {
         for (int t = 0; t < N2; ++t) passB1_from_lds<N, -1>(regs[t].data(), z.data(), t);
@@ -87,12 +89,18 @@ static int check_line() {
     double ef = direct_err(x, X, -1);
     // inverse back from the pass-B distribution
     if constexpr (Fact<N>::L == 1) {
-        for (int t = 0; t < N2; ++t) passB1inv_to_lds<N, +1>(regs[t].data(), z.data(), t, tw.data());
+        for (int t = 0; t < N2; ++t) {
+            cf w[N1];
+            twiddles_binv<N, +1>(w, t, tw.data());
+            passB1inv_to_lds<N, +1>(regs[t].data(), z.data(), t, w);
+        }
     } else {
         auto held = regs;
         for (int t = 0; t < N2; ++t) {
             passB2inv_combine<N, +1>(regs[t].data(), held[t ^ 1].data(), t);
-            passB2inv_local_to_lds<N, +1>(regs[t].data(), z.data(), t, tw.data());
+            cf w[N1];
+            twiddles_binv<N, +1>(w, t, tw.data());
+            passB2inv_local_to_lds<N, +1>(regs[t].data(), z.data(), t, w);
         }
     }
     double eb = 0, den = 0;
