@@ -348,9 +348,20 @@ def run_adam_vs_epie(epochs, minibatch, lr, max_sweeps):
     }
 
 
-def cpu_baseline(cfg_id, budget_s):
+def _oracle_batch(oracle, O, P, wl, idx):
+    """One coloured batch through the oracle, handed only that batch's
+    positions and patterns (re-indexed): the oracle prepares every pattern
+    it is given on each call, so passing the whole workload per batch would
+    time that preparation, not the update."""
+    O, P, _, _ = oracle.sweep_coloured(O, P, wl.positions[idx], wl.intensities[idx],
+                                       np.arange(len(idx)), [0, len(idx)], check=False)
+    return O, P
+
+
+def cpu_baseline(cfg_id, budget_s, wl256=None):
     """The FP64 oracle on the host: coloured sweep over the same workload's
-    first batches until ``budget_s`` seconds of work are done."""
+    first batches until ``budget_s`` seconds of work are done (and briefly
+    the other pattern sizes, see cpu_other_configs)."""
     import oracle
     import sim
     from paper_2308_10674_amd import colour
@@ -365,7 +376,7 @@ def cpu_baseline(cfg_id, budget_s):
     b = 0
     while time.perf_counter() - t0 < budget_s and b < nc:
         idx = base[off[b]:off[b + 1]]
-        O, P, _, _ = oracle.sweep_coloured(O, P, wl.positions, wl.intensities, idx, [0, len(idx)], check=False)
+        O, P = _oracle_batch(oracle, O, P, wl, idx)
         done += len(idx)
         b += 1
     dt = time.perf_counter() - t0
@@ -376,7 +387,51 @@ def cpu_baseline(cfg_id, budget_s):
     return dict(value=done / dt, unit="position updates/s", cores=1, kind="oracle",
                 sample=f"FP64 numpy oracle, coloured batches 0..{b - 1} of one sweep "
                        f"({done} of {wl.count} position updates, {dt:.1f} s, single thread)",
-                host_cpus={"cpu_count": os.cpu_count(), "affinity": affinity})
+                host_cpus={"cpu_count": os.cpu_count(), "affinity": affinity},
+                other_configs=cpu_other_configs(max(1.0, budget_s / 5), wl256))
+
+
+def cpu_other_configs(budget_s, wl256=None):
+    """The same oracle on the other two pattern sizes, briefly: the 32 px
+    raster swept strictly (sequential ePIE, whole sweeps) and, when the
+    256 px spiral workload is at hand, the first coloured batches of its
+    schedule, each for about ``budget_s`` seconds."""
+    import oracle
+    import sim
+    from paper_2308_10674_amd import colour
+
+    out = []
+    wl = sim.make_config(0)
+    O, P = wl.object0, wl.probe0
+    done, s = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        order = sim.sweep_order(wl.seed, s, wl.count)
+        O, P, _, _ = oracle.sweep_strict(O, P, wl.positions, wl.intensities, order)
+        done += len(order)
+        s += 1
+    dt = time.perf_counter() - t0
+    out.append({"workload": "32 px patterns, 10x10 raster, strict (sequential) ePIE", "value": done / dt,
+                "unit": "position updates/s", "sample": f"{s} whole sweeps, {done} updates, {dt:.1f} s"})
+    if wl256 is None:
+        return out
+    wl = wl256
+    col, nc = colour(wl.positions, wl.n)
+    base = np.argsort(col, kind="stable")
+    off = np.concatenate([[0], np.cumsum(np.bincount(col))])
+    O, P = wl.object0, wl.probe0
+    done, b = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and b < nc:
+        idx = base[off[b]:off[b + 1]]
+        O, P = _oracle_batch(oracle, O, P, wl, idx)
+        done += len(idx)
+        b += 1
+    dt = time.perf_counter() - t0
+    out.append({"workload": "256 px patterns, 20000-position Fermat spiral, coloured batches",
+                "value": done / dt, "unit": "position updates/s",
+                "sample": f"coloured batches 0..{b - 1}, {done} updates, {dt:.1f} s"})
+    return out
 
 
 def main():
@@ -462,8 +517,10 @@ def main():
     if not args.no_forms:
         out["forms"] = run_forms(wl, args.steps)
         out["live"] = run_live(wl, tiles[0])
+    wl256 = None
     if not args.no_256:
         r2 = run_gpu(2, args.steps_256, 1, args.form, tile=tiles[1])
+        wl256 = r2["wl"]
         out["n256"] = {
             "value": round(r2["rate"], 1), "unit": "position updates/s",
             "ms_per_step": round(r2["ms"] / args.steps_256, 3), "steps": args.steps_256,
@@ -476,7 +533,7 @@ def main():
     if not args.no_multi:
         out["multi16"] = run_multi(args.steps_multi, 1)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds, wl256)
     print(json.dumps(out), flush=True)
 
 
