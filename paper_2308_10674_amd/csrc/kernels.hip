@@ -127,8 +127,8 @@ __device__ inline double block_sum(double v, double* sh) {
 // Forward row stage: RB rows of one position per workgroup; column stage: CB
 // columns.  Small tiles spread a position over many compute units (a batch
 // holds only a few dozen positions, so the stages are latency-bound).  At
-// 128 px (16 threads per line) 8 rows and 16 columns measured best; 8
-// columns per workgroup were markedly slower.
+// 128 px (16 threads per line) 4 rows (one wave per workgroup) and 16
+// columns measured best; 8 or 32 columns per workgroup were slower.
 #ifndef PTYC_RB64
 #define PTYC_RB64 16
 #endif
@@ -136,7 +136,7 @@ __device__ inline double block_sum(double v, double* sh) {
 #define PTYC_CB64 16
 #endif
 #ifndef PTYC_RB128
-#define PTYC_RB128 8
+#define PTYC_RB128 4
 #endif
 #ifndef PTYC_CB128
 #define PTYC_CB128 16
@@ -201,9 +201,10 @@ template <> struct Variants<64> {
     static constexpr TileV v[K] = {{Tile<64>::RB, Tile<64>::CB, ITile<64>::R, ITile<64>::S}, {32, 32, 4, 8}};
 };
 template <> struct Variants<128> {
-    static constexpr int K = 4;
+    static constexpr int K = 5;
     static constexpr TileV v[K] = {
-        {Tile<128>::RB, Tile<128>::CB, ITile<128>::R, ITile<128>::S}, {16, 16, 1, 40}, {8, 16, 1, 32}, {16, 16, 1, 32}};
+        {Tile<128>::RB, Tile<128>::CB, ITile<128>::R, ITile<128>::S}, {8, 16, 1, 40}, {16, 16, 1, 40},
+        {4, 16, 1, 32}, {8, 16, 1, 32}};
 };
 template <> struct Variants<256> {
     static constexpr int K = 3;
