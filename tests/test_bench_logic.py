@@ -43,3 +43,25 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_cpu_baseline_batches_compute_the_oracle_sweep():
+    """The CPU baseline hands each oracle call only its batch's positions and
+    patterns; a sweep of such calls equals the oracle's own coloured sweep
+    over the whole workload, bit for bit."""
+    import numpy as np
+
+    import oracle
+    import sim
+    from paper_2308_10674_amd import colour
+
+    wl = sim.make_config(0)
+    col, nc = colour(wl.positions, wl.n)
+    order = np.argsort(col, kind="stable")
+    off = np.concatenate([[0], np.cumsum(np.bincount(col))])
+    O_ref, P_ref, _, _ = oracle.sweep_coloured(wl.object0, wl.probe0, wl.positions, wl.intensities, order, off)
+    O, P = wl.object0, wl.probe0
+    for b in range(nc):
+        O, P = bench._oracle_batch(oracle, O, P, wl, order[off[b]:off[b + 1]])
+    np.testing.assert_array_equal(O, O_ref)
+    np.testing.assert_array_equal(P, P_ref)
