@@ -93,20 +93,6 @@ __device__ inline double wave_sum(double v) {
     return (lane_of(v, 0) + lane_of(v, 16)) + (lane_of(v, 32) + lane_of(v, 48));
 }
 
-// block-wide max; every thread gets the result
-template <int NT>
-__device__ inline float block_max(float v, float* sh) {
-    v = wave_max(v);
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    float m = sh[0];
-#pragma unroll
-    for (int i = 1; i < NT / kWave; ++i) m = fmaxf(m, sh[i]);
-    __syncthreads();
-    return m;
-}
-
 // block-wide sum in a fixed order; the result is valid in thread 0
 template <int NT>
 __device__ inline double block_sum(double v, double* sh) {
@@ -265,8 +251,7 @@ __device__ __forceinline__ void store_through(cf* p, cf v) {
 // each row, spectrum rows to scratch; partial max |S_j O|^2 to winmax, one
 // entry per wave (no workgroup barrier: a maximum is exact in any order).
 template <int N, int RB>
-__device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds,
-                                               float* red) {
+__device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds) {
     using g = RowG<N, RB>;
     const int t = threadIdx.x % g::T, rl = threadIdx.x / g::T;
     cf w[g::N1];
@@ -371,8 +356,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 // P_{b+1} written for the block.  bsize == 0 only refreshes the block's
 // max |P|^2.
 template <int N, int R, int S, int MODE = kModeEpie>
-__device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl,
-                                               float* red) {
+__device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl) {
     using g = InvG<N, R, S>;
     const int t = threadIdx.x % g::T;
     const int rl = (threadIdx.x / g::T) % g::R;
@@ -531,11 +515,10 @@ template <int N, int RB = Tile<N>::RB, bool DEV = false>
 __global__ __launch_bounds__((RowG<N, RB>::NT)) void k_rows_fwd(BatchArgs a) {
     using g = RowG<N, RB>;
     __shared__ cf lds[RB * Lds<N>::LINE];
-    __shared__ float red[g::NT / kWave];
     const BatchArgs b = DEV ? resolved(a) : a;
     const int slot = blockIdx.x / g::G;
     if (DEV && slot >= b.bsize) return;   // a grid sized for a larger batch (whole workgroup)
-    stage_rows_fwd<N, RB>(b, slot, blockIdx.x % g::G, lds, red);
+    stage_rows_fwd<N, RB>(b, slot, blockIdx.x % g::G, lds);
 }
 
 template <int N, int CB = Tile<N>::CB, bool DEV = false>
@@ -554,8 +537,7 @@ __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     using g = InvG<N, R, S>;
     __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
     __shared__ cf dl[g::S * g::R * N];
-    __shared__ float red[g::NT / kWave];
-    stage_rows_inv<N, g::R, g::S>(DEV ? resolved(a) : a, blockIdx.x, lds, dl, red);
+    stage_rows_inv<N, g::R, g::S>(DEV ? resolved(a) : a, blockIdx.x, lds, dl);
 }
 
 // Several reconstructions at once: workgroup b belongs to descriptor i with
@@ -578,11 +560,10 @@ __global__ __launch_bounds__(kRowNT<N>) void k_rows_fwd_multi(MultiArgs m) {
     constexpr int RB = Tile<N>::RB;
     using g = RowG<N, RB>;
     __shared__ cf lds[RB * Lds<N>::LINE];
-    __shared__ float red[g::NT / kWave];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
-    stage_rows_fwd<N, RB>(a, local / g::G, local % g::G, lds, red);
+    stage_rows_fwd<N, RB>(a, local / g::G, local % g::G, lds);
 }
 
 template <int N>
@@ -602,10 +583,9 @@ __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
     using g = InvG<N>;
     __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
     __shared__ cf dl[g::S * g::R * N];
-    __shared__ float red[g::NT / kWave];
     const int i = (int)blockIdx.x / g::GI;
     const BatchArgs a = m.tab[i];
-    stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds, dl, red);
+    stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds, dl);
 }
 
 // Mixed pattern sizes in one launch per stage.  Every size in {64, 128,
@@ -630,10 +610,10 @@ constexpr int kMixInvLdsMax = cmax3(kMixInvLds<64>, kMixInvLds<128>, kMixInvLds<
 constexpr int kMixInvDlMax = cmax3(kMixInvDl<64>, kMixInvDl<128>, kMixInvDl<256>);
 
 template <int N>
-__device__ __forceinline__ void mix_rows_fwd(const BatchArgs& a, int local, cf* lds, float* red) {
+__device__ __forceinline__ void mix_rows_fwd(const BatchArgs& a, int local, cf* lds) {
     using g = RowG<N, MixTile<N>::RB>;
     static_assert(g::NT == kMixRowNT, "mixed row tile");
-    stage_rows_fwd<N, MixTile<N>::RB>(a, local / g::G, local % g::G, lds, red);
+    stage_rows_fwd<N, MixTile<N>::RB>(a, local / g::G, local % g::G, lds);
 }
 
 template <int N>
@@ -644,22 +624,21 @@ __device__ __forceinline__ void mix_cols(const BatchArgs& a, int local, cf* lds,
 }
 
 template <int N>
-__device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* lds, cf* dl, float* red) {
+__device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* lds, cf* dl) {
     using g = InvG<N, MixTile<N>::R, MixTile<N>::S>;
     static_assert(g::NT == kMixInvNT, "mixed inverse tile");
-    stage_rows_inv<N, g::R, g::S>(a, local, lds, dl, red);
+    stage_rows_inv<N, g::R, g::S>(a, local, lds, dl);
 }
 
 __global__ __launch_bounds__(kMixRowNT) void k_rows_fwd_mix(MultiArgs m) {
     __shared__ cf lds[kMixRowLdsMax];
-    __shared__ float red[kMixRowNT / kWave];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
     switch (a.n) {
-        case 64: mix_rows_fwd<64>(a, local, lds, red); break;
-        case 128: mix_rows_fwd<128>(a, local, lds, red); break;
-        case 256: mix_rows_fwd<256>(a, local, lds, red); break;
+        case 64: mix_rows_fwd<64>(a, local, lds); break;
+        case 128: mix_rows_fwd<128>(a, local, lds); break;
+        case 256: mix_rows_fwd<256>(a, local, lds); break;
     }
 }
 
@@ -679,14 +658,13 @@ __global__ __launch_bounds__(kMixRowNT) void k_cols_mix(MultiArgs m) {
 __global__ __launch_bounds__(kMixInvNT) void k_rows_inv_mix(MultiArgs m) {
     __shared__ cf lds[kMixInvLdsMax];
     __shared__ cf dl[kMixInvDlMax];
-    __shared__ float red[kMixInvNT / kWave];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
     switch (a.n) {
-        case 64: mix_rows_inv<64>(a, local, lds, dl, red); break;
-        case 128: mix_rows_inv<128>(a, local, lds, dl, red); break;
-        case 256: mix_rows_inv<256>(a, local, lds, dl, red); break;
+        case 64: mix_rows_inv<64>(a, local, lds, dl); break;
+        case 128: mix_rows_inv<128>(a, local, lds, dl); break;
+        case 256: mix_rows_inv<256>(a, local, lds, dl); break;
     }
 }
 
@@ -724,8 +702,7 @@ __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_grad(BatchArgs a) 
     using g = InvG<N, R, S>;
     __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
     __shared__ cf dl[g::S * g::R * N];
-    __shared__ float red[g::NT / kWave];
-    stage_rows_inv<N, g::R, g::S, kModeGrad>(a, blockIdx.x, lds, dl, red);
+    stage_rows_inv<N, g::R, g::S, kModeGrad>(a, blockIdx.x, lds, dl);
 }
 
 __global__ __launch_bounds__(256) void k_fill_zero(cf* p, int64_t n) {
@@ -777,7 +754,6 @@ __global__ __launch_bounds__(kSweepNT<N>) void k_sweep(BatchArgs a, SweepCtl c) 
     __shared__ cf lds[LINES * Lds<N>::LINE];
     __shared__ cf dl[ig::S * ig::R * N];
     __shared__ double redd[NT / kWave];
-    __shared__ float redf[NT / kWave];
     __shared__ int ok_sh;
     unsigned epoch = 0;
     for (int b = 0; b < c.nb; ++b) {
@@ -787,13 +763,13 @@ __global__ __launch_bounds__(kSweepNT<N>) void k_sweep(BatchArgs a, SweepCtl c) 
         a.off = off;
         a.bsize = bs;
         for (int it = blockIdx.x; it < bs * rg::G; it += gridDim.x)
-            stage_rows_fwd<N, TB>(a, it / rg::G, it % rg::G, lds, redf);
+            stage_rows_fwd<N, TB>(a, it / rg::G, it % rg::G, lds);
         if (!grid_barrier(c, ++epoch, &ok_sh)) return;
         for (int it = blockIdx.x; it < bs * cg::GC; it += gridDim.x)
             stage_cols<N, TB>(a, it / cg::GC, it % cg::GC, lds, redd);
         if (!grid_barrier(c, ++epoch, &ok_sh)) return;
         for (int it = blockIdx.x; it < ig::GI; it += gridDim.x)
-            stage_rows_inv<N, ig::R, ig::S>(a, it, lds, dl, redf);
+            stage_rows_inv<N, ig::R, ig::S>(a, it, lds, dl);
         if (!grid_barrier(c, ++epoch, &ok_sh)) return;
         // the maxima just written are those of the next batch's probe
         float* const next_in = a.pmax_out;
