@@ -12,8 +12,8 @@ Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this package; the library never calls it.
 """
 from .epie import (  # noqa: F401
-    dft2_bruteforce, fft2, ifft2, sgn, exit_wave, modulus_replace,
-    position_update, sweep_strict, sweep_coloured, fourier_error_terms,
+    dft2_bruteforce, fft2, ifft2, sgn, modulus_replace,
+    position_update, sweep_strict, sweep_coloured,
     check_schedule, greedy_colouring, windows_overlap, rel_l2, union_mask,
     reconstruct,
 )

@@ -81,13 +81,6 @@ def sgn(z):
     return out
 
 
-def exit_wave(probe, obj, yx):
-    """psi = P * S_j O for the window whose top-left corner is yx."""
-    n = probe.shape[0]
-    y, x = int(yx[0]), int(yx[1])
-    return probe * obj[y:y + n, x:x + n]
-
-
 def modulus_replace(Psi, sqrt_i, mask=None):
     """Psi' = sqrt(I) * sgn(Psi): keep the phase, impose the measured modulus.
     Where ``mask`` is False there is no measurement and Psi' = Psi."""
@@ -195,21 +188,6 @@ def sweep_coloured(obj, probe, positions, intensities, order, batch_offsets,
             acc = acc + d[s]
         P = P + (beta / len(idx)) * acc
     return O, P, num, den
-
-
-def fourier_error_terms(obj, probe, positions, intensities, idx=None):
-    """(sum_j sum_k (|F(P S_j O)| - sqrt I_j)^2, sum_j sum_k I_j) for the
-    current state, without updating anything."""
-    n = probe.shape[0]
-    idx = range(len(positions)) if idx is None else idx
-    num = 0.0
-    den = 0.0
-    for j in idx:
-        Psi = fft2(exit_wave(probe, obj, positions[j]))
-        I = np.asarray(intensities[j], dtype=np.float64)
-        num += float(np.sum((np.abs(Psi) - np.sqrt(I)) ** 2))
-        den += float(np.sum(I))
-    return num, den
 
 
 # ---------------------------------------------------------------- schedules

@@ -63,16 +63,27 @@ def fp32_floor(O, P, wl, order, off, mask, count=None, angles=(0.3, 1.1, 2.0, 3.
 
 
 def gate(floor):
-    """The parity bar: 1e-5, unless FP32 rounding alone (the oracle in
-    complex64) already moves this sweep further, then three times that."""
+    """The bar of a cold-start row: 1e-5, unless FP32 rounding alone (the
+    oracle in complex64) already moves it further, then three times that."""
     return max(RTOL, 3.0 * floor)
+
+
+def is_cold_start(wl, O, P):
+    """The state is the paper's starting values as the workload holds them:
+    a flat object and a real Gaussian probe centred on the pattern (so its
+    first spectrum is real up to a sign pattern and falls below FP32
+    resolution over most of the pattern)."""
+    return (np.array_equal(O, wl.object0) and np.array_equal(P, wl.probe0)
+            and not np.any(np.imag(wl.probe0)) and not np.any(wl.object0 - wl.object0.flat[0]))
 
 
 def run_resynced(eng, wl, n_sweeps, schedule, count=None, start=None, label=""):
     """For each sweep: take its (order, offsets) from ``schedule(s)``, reset
     the GPU to the oracle's state, run one sweep on both, compare.  Returns
-    the rows (also printed) and the oracle's final (object, probe).  A
-    sweep that misses 1e-5 is measured against the FP32 floor."""
+    the rows (also printed) and the oracle's final (object, probe).  A row
+    is ``cold`` when its sweep starts from the paper's starting values;
+    only such a row is measured against the FP32 floor when it misses
+    1e-5."""
     count = wl.count if count is None else count
     mask = oracle.union_mask(wl.positions[:count], wl.n, wl.h, wl.w)
     O, P = (wl.object0, wl.probe0) if start is None else start
@@ -81,17 +92,18 @@ def run_resynced(eng, wl, n_sweeps, schedule, count=None, start=None, label=""):
         order, off = schedule(s)
         if off is not None:
             oracle.check_schedule(wl.positions[:count], wl.n, order, off)
+        cold = is_cold_start(wl, O, P)
         eng.set_object(O.astype(np.complex64))
         eng.set_probe(P.astype(np.complex64))
         err = eng.sweep(1, order=order, batch_offsets=off, errors=True)[0]
         Og, Pg = eng.get_object(), eng.get_probe()
         On, Pn, num, den = oracle_sweep(O, P, wl, order, off, count=count)
         e_orc = num / den
-        row = dict(sweep=s, rel_o=oracle.rel_l2(Og, On, mask), rel_p=oracle.rel_l2(Pg, Pn),
+        row = dict(sweep=s, cold=cold, rel_o=oracle.rel_l2(Og, On, mask), rel_p=oracle.rel_l2(Pg, Pn),
                    rel_err=abs(float(err) - e_orc) / e_orc if e_orc > 0 else abs(float(err)),
                    err_gpu=float(err), err_orc=e_orc, floor_o=0.0, floor_p=0.0, floor_err=0.0,
                    untouched_equal=bool(np.array_equal(Og[~mask], O.astype(np.complex64)[~mask])))
-        if max(row["rel_o"], row["rel_p"], row["rel_err"]) > RTOL:
+        if cold and max(row["rel_o"], row["rel_p"], row["rel_err"]) > RTOL:
             row["floor_o"], row["floor_p"], row["floor_err"] = fp32_floor(O, P, wl, order, off, mask, count=count)
         print(label, row, flush=True)
         progress(f"{label}: sweep {s} compared")
@@ -101,16 +113,17 @@ def run_resynced(eng, wl, n_sweeps, schedule, count=None, start=None, label=""):
 
 
 def check_rows(rows, final=None, factor=10.0):
-    """Per-sweep bar: 1e-5, or ``factor`` times the FP32 floor when FP32
-    rounding alone already exceeds it.  Along a sweep of a hundred or more
-    dependent batches rounding differences are amplified by the iteration
-    itself, and how much depends on where they fall, so two FP32
-    implementations of equal per-batch accuracy can differ several-fold
-    here; the strict check of every kernel is the per-batch one."""
+    """Per-sweep bar: 1e-5 relative L2 on object, probe and running error.
+    Only a sweep that starts from the paper's starting values (``cold``)
+    may instead stay within ``factor`` times the FP32 floor of object and
+    probe: its first batch is decided by FP32 rounding in any FP32
+    implementation, and the rest of the sweep (its running error included)
+    carries that difference."""
     for r in rows:
-        assert r["rel_o"] <= max(RTOL, factor * r["floor_o"]), r
-        assert r["rel_p"] <= max(RTOL, factor * r["floor_p"]), r
-        assert r["rel_err"] <= max(RTOL, factor * r["floor_err"]), r
+        cold = r["cold"]
+        assert r["rel_o"] <= (max(RTOL, factor * r["floor_o"]) if cold else RTOL), r
+        assert r["rel_p"] <= (max(RTOL, factor * r["floor_p"]) if cold else RTOL), r
+        assert r["rel_err"] <= (max(RTOL, factor * r["floor_err"]) if cold else RTOL), r
         assert r["untouched_equal"], r
 
 
@@ -118,7 +131,8 @@ def run_batches_resynced(eng, wl, order, off, count=None, start=None, label="", 
     """Every batch of one sweep (or the listed ones) re-synced: the GPU
     starts the batch from the oracle's state rounded to complex64 and runs
     that batch alone; object (over the batch's windows), probe and the
-    batch's error numerator are compared.  Returns rows and the oracle's
+    batch's error numerator are compared.  A row is ``cold`` when its batch
+    starts from the paper's starting values.  Returns rows and the oracle's
     state after the sweep (when all batches ran)."""
     count = wl.count if count is None else count
     pos, inten = wl.positions[:count], wl.intensities[:count]
@@ -129,6 +143,7 @@ def run_batches_resynced(eng, wl, order, off, count=None, start=None, label="", 
         idx = np.asarray(order[off[b]:off[b + 1]])
         if len(idx) == 0:
             continue
+        cold = is_cold_start(wl, O, P)
         eng.set_object(O.astype(np.complex64))
         eng.set_probe(P.astype(np.complex64))
         e = eng.sweep(1, order=idx, batch_offsets=None if eng.mode == "strict" else [0, len(idx)],
@@ -137,10 +152,11 @@ def run_batches_resynced(eng, wl, order, off, count=None, start=None, label="", 
         On, Pn, num, den = oracle_sweep(O, P, wl, idx, None if eng.mode == "strict" else [0, len(idx)],
                                         count=count)
         m = oracle.union_mask(pos[idx], wl.n, wl.h, wl.w)
-        row = dict(batch=int(b), size=int(len(idx)), rel_o=oracle.rel_l2(Og, On, m), rel_p=oracle.rel_l2(Pg, Pn),
-                   rel_err=abs(float(e) - num / den) / (num / den), floor_o=0.0, floor_p=0.0, floor_err=0.0,
+        row = dict(batch=int(b), size=int(len(idx)), cold=cold, rel_o=oracle.rel_l2(Og, On, m),
+                   rel_p=oracle.rel_l2(Pg, Pn), rel_err=abs(float(e) - num / den) / (num / den),
+                   floor_o=0.0, floor_p=0.0, floor_err=0.0,
                    outside_equal=bool(np.array_equal(Og[~m], O.astype(np.complex64)[~m])))
-        if max(row["rel_o"], row["rel_p"], row["rel_err"]) > RTOL:
+        if cold and max(row["rel_o"], row["rel_p"]) > RTOL:
             off1 = None if eng.mode == "strict" else [0, len(idx)]
             row["floor_o"], row["floor_p"], row["floor_err"] = fp32_floor(O, P, wl, idx, off1, m, count=count)
         rows.append(row)
@@ -148,18 +164,26 @@ def run_batches_resynced(eng, wl, order, off, count=None, start=None, label="", 
             O, P = On, Pn
     worst = max(rows, key=lambda r: max(r["rel_o"], r["rel_p"], r["rel_err"])) if rows else None
     print(label, f"{len(rows)} batches re-synced, worst", worst, flush=True)
+    cold_rows = [r for r in rows if r["cold"]]
+    if cold_rows:
+        print(label, "cold-start batch", cold_rows[0], flush=True)
     progress(f"{label}: {len(rows)} batches re-synced")
     return rows, (O, P)
 
 
 def check_batches(rows):
-    """Per-batch bar: 1e-5 relative L2 on object, probe and error numerator;
-    only a batch whose spectrum falls below FP32 resolution (the first batch
-    from a real, even start) is held to three times the FP32 floor."""
+    """Per-batch bar: 1e-5 relative L2 on object, probe and error numerator.
+    The one exception is the batch that starts from the paper's starting
+    values (flat object, real even Gaussian probe): its spectrum falls below
+    FP32 resolution, so its object and probe are held to three times the
+    FP32 oracle's own deviation instead (its error numerator still to
+    1e-5).  The exception fires nowhere else."""
     for r in rows:
-        assert r["rel_o"] <= gate(r["floor_o"]), r
-        assert r["rel_p"] <= gate(r["floor_p"]), r
-        assert r["rel_err"] <= gate(r["floor_err"]), r
+        lim_o = gate(r["floor_o"]) if r["cold"] else RTOL
+        lim_p = gate(r["floor_p"]) if r["cold"] else RTOL
+        assert r["rel_o"] <= lim_o, r
+        assert r["rel_p"] <= lim_p, r
+        assert r["rel_err"] <= RTOL, r
         assert r["outside_equal"], r
 
 

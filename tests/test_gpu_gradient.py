@@ -39,6 +39,96 @@ def problem(torch_cuda):
     return dict(wl=wl, eng=eng, O=O.astype(np.complex64), P=P.astype(np.complex64), to=to, tp=tp, idx=idx)
 
 
+def _near_truth(wl, seed):
+    """An estimate near the truth: the object with a 0.15 rad random phase
+    error, the probe with 5 % random amplitude error (complex64)."""
+    rng = np.random.default_rng(seed)
+    O = wl.object_true * np.exp(0.15j * rng.standard_normal(wl.object_true.shape))
+    P = wl.probe_true * (1 + 0.05 * rng.standard_normal(wl.probe_true.shape))
+    return O.astype(np.complex64), P.astype(np.complex64)
+
+
+def _compare(torch, eng, wl, O, P, idx):
+    """Loss and both gradients of the GPU against the FP64 adjoint taken at
+    the same complex64 estimate: (rel loss, rel-L2 grad O over the windows,
+    rel-L2 grad P, grad O outside the windows all zero)."""
+    to = torch.from_numpy(O).cuda()
+    tp = torch.from_numpy(P).cuda()
+    L, go, gp = eng.amp_loss(to, tp, idx, grad=True)
+    Lo, go_o, gp_o = oracle.amplitude_loss_grad(O, P, wl.positions, wl.intensities, idx)
+    mask = oracle.union_mask(wl.positions[idx], wl.n, wl.h, wl.w)
+    go = go.cpu().numpy()
+    gp = gp.cpu().numpy()
+    return abs(L - Lo) / Lo, oracle.rel_l2(go, go_o, mask), oracle.rel_l2(gp, gp_o), bool(np.all(go[~mask] == 0))
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+def test_gradient_every_size(n, torch_cuda):
+    """Loss, dL/dO and dL/dP element-wise against the FP64 adjoint at every
+    pattern size the library supports: a 5 x 5 raster with overlapping
+    windows (step n/3), all 25 positions in one minibatch, so the adjoint's
+    scatter-add runs over several colours."""
+    from paper_2308_10674_amd import Engine
+    step = max(1, n // 3)
+    m = n + 4 * step + 8
+    pos = sim.raster_positions(5, step, n, m, 1, 40 + n)
+    wl = sim.make_workload(n, m, 0.3 * n, 0.5 / (0.3 * n), pos, 1e6, 40 + n)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(wl.positions, wl.intensities)
+    O, P = _near_truth(wl, 41 + n)
+    idx = np.random.default_rng(n).permutation(wl.count)
+    rl, ro, rp, zero_out = _compare(torch_cuda, eng, wl, O, P, idx)
+    print(f"n={n} loss {rl:.2e} grad O {ro:.2e} grad P {rp:.2e}", flush=True)
+    assert rl <= RTOL and ro <= RTOL and rp <= RTOL
+    assert zero_out
+
+
+def test_gradient_finite_difference_subproblem(torch_cuda):
+    """The 32 px, 10-position subproblem on a 64^2 object on which the
+    oracle's adjoint is pinned to FP64 central differences: the GPU's
+    gradients against that adjoint (1e-5 relative L2), and the GPU's
+    directional derivatives Re<grad, V> against FP64 central differences
+    of the oracle's loss along random directions (bar 5e-5: the 2e-5 at
+    which the oracle's own adjoint meets those differences plus the 1e-5
+    parity bar)."""
+    torch = torch_cuda
+    from paper_2308_10674_amd import Engine
+    wl = sim.make_workload(32, 64, 10.0, 0.05, sim.raster_positions(4, 8, 32, 64, 1, 21)[:10], 1e6, 21,
+                           noise=True, dtype=np.float64)
+    rng = np.random.default_rng(22)
+    O = (wl.object_true * np.exp(0.2j * rng.standard_normal(wl.object_true.shape))).astype(np.complex64)
+    P = (wl.probe0 + 0.1 * (rng.standard_normal(wl.probe0.shape) + 1j * rng.standard_normal(wl.probe0.shape))
+         * np.abs(wl.probe0).max()).astype(np.complex64)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(wl.positions, wl.intensities.astype(np.float32))
+    wl.intensities = wl.intensities.astype(np.float32).astype(np.float64)   # what the GPU holds
+    idx = np.arange(wl.count)
+    rl, ro, rp, zero_out = _compare(torch, eng, wl, O, P, idx)
+    print(f"fd subproblem: loss {rl:.2e} grad O {ro:.2e} grad P {rp:.2e}", flush=True)
+    assert rl <= RTOL and ro <= RTOL and rp <= RTOL and zero_out
+    _, go, gp = eng.amp_loss(torch.from_numpy(O).cuda(), torch.from_numpy(P).cuda(), idx, grad=True)
+    go = go.cpu().numpy().astype(np.complex128)
+    gp = gp.cpu().numpy().astype(np.complex128)
+    O64, P64 = O.astype(np.complex128), P.astype(np.complex128)
+    drng = np.random.default_rng(23)
+    for _ in range(3):
+        for which in ("O", "P"):
+            base = O64 if which == "O" else P64
+            V = drng.standard_normal(base.shape) + 1j * drng.standard_normal(base.shape)
+            h = 1e-6 * (1.0 if which == "O" else np.abs(P64).max())
+            if which == "O":
+                fp = oracle.amplitude_loss(O64 + h * V, P64, wl.positions, wl.intensities)
+                fm = oracle.amplitude_loss(O64 - h * V, P64, wl.positions, wl.intensities)
+                ana = np.real(np.vdot(go, V))
+            else:
+                fp = oracle.amplitude_loss(O64, P64 + h * V, wl.positions, wl.intensities)
+                fm = oracle.amplitude_loss(O64, P64 - h * V, wl.positions, wl.intensities)
+                ana = np.real(np.vdot(gp, V))
+            fd = (fp - fm) / (2 * h)
+            print("fd", which, fd, ana, flush=True)
+            assert abs(fd - ana) <= 5e-5 * abs(fd), (which, fd, ana)
+
+
 def test_loss_matches_oracle(problem):
     pr = problem
     L = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"])
