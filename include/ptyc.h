@@ -171,6 +171,30 @@ int ptyc_sweep(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
                int64_t order_len, const int64_t* batch_offsets,
                int64_t n_batches, double* err_out);
 
+/* ptyc_sweep for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sweeps with the same arguments, schedule, result bytes and errors as
+ * ptyc_sweep in the per-batch launch form (PTYC_FORM_BATCH, the context's
+ * tile variant), but every per-call buffer (the spectrum exchange between
+ * the stages, the partial maxima of the windows, the error partials and
+ * sums, the device copy of a sweep's order) lives in one fixed device array
+ * of PTYC_NOALLOC_BYTES bytes that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree, pinned host memory or torch allocation); the context's own
+ * buffers (object, probe, patterns) were allocated by init and
+ * add_positions.  The orders are copied from pageable host memory, one
+ * sweep at a time, and the call synchronises the stream before it returns.
+ * Work memory needed: about 16 B per position of a sweep, 8 N^2 B per
+ * position of the largest batch, 8 B per error partial and 8 B per sweep;
+ * PTYC_ERR_ARG (nothing run) if that exceeds PTYC_NOALLOC_BYTES.  All calls
+ * on one GPU share that array, whose contents are left from the last call:
+ * calls that overlap in time on one GPU (other threads, other streams)
+ * race on it and must be serialised by the caller. */
+#define PTYC_NOALLOC_BYTES 33554432   /* 32 MiB */
+int ptyc_sweep_noalloc(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
+                       int64_t order_len, const int64_t* batch_offsets,
+                       int64_t n_batches, double* err_out);
+
 /* Run n_sweeps sweeps on each of n_ctx independent contexts together
  * (several scans of uneven size and pattern size at once).  Every context
  * follows its own default schedule, exactly as ptyc_sweep(ctx, n_sweeps,

@@ -22,6 +22,7 @@ PTYC_FORM_BATCH = 1
 PTYC_FORM_PERSISTENT = 2
 PTYC_FORM_GRAPH = 3
 PTYC_TILE_MAX = 8
+PTYC_NOALLOC_BYTES = 32 << 20
 PTYC_KERNEL_ROWS_FWD = 0
 PTYC_KERNEL_COLS = 1
 PTYC_KERNEL_ROWS_INV = 2
@@ -62,6 +63,7 @@ SIGNATURES = {
     "ptyc_init": (C.c_int, [C.POINTER(_P), C.POINTER(Config), _P, _P, C.c_int, _P]),
     "ptyc_add_positions": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int]),
     "ptyc_sweep": (C.c_int, [_P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64, _DP]),
+    "ptyc_sweep_noalloc": (C.c_int, [_P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64, _DP]),
     "ptyc_sweep_multi": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP]),
     "ptyc_average": (C.c_int, [C.POINTER(_P), C.c_int32]),
     "ptyc_get_schedule": (C.c_int, [_P, _I64P, _I64P, _I64P]),

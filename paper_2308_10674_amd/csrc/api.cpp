@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,9 +16,42 @@
 
 using namespace ptyc;
 
+// Work memory of ptyc_sweep_noalloc (the spectrum exchange, the partial
+// maxima of the windows, the error partials and sums, the device copy of a
+// sweep's order): a file-scope device array, so that entry point allocates
+// nothing.  Every GPU the library runs on holds its own copy until the
+// process ends.  Host code never hands the array's name to a kernel (on the
+// host it only names a stand-in); its device address on each device is
+// taken once with hipGetSymbolAddress (noalloc_setup, from ptyc_init) and
+// that pointer is used instead.
+constexpr size_t kNoallocBytes = PTYC_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `device` (current), taken once
+hipError_t noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* noalloc_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return g_noalloc_ptr[device];
+}
 
 struct DevBuf {
     void* p = nullptr;
@@ -352,6 +386,12 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     c->ingest.scale = 1.0f;
     c->ingest.flags = cfg->flags;
     (void)hipGetDevice(&c->device);
+    if ((e = noalloc_setup(c->device)) != hipSuccess) {
+        hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+        g_init_error = c->err;
+        ptyc_destroy(c);
+        return PTYC_ERR_HIP;
+    }
 
     const int n = cfg->n;
     const size_t obj_bytes = (size_t)cfg->h * cfg->w * sizeof(cf);
@@ -947,6 +987,83 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return check_fault(c);
     }
+    return PTYC_OK;
+}
+
+int ptyc_sweep_noalloc(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t order_len,
+                       const int64_t* off, int64_t n_batches, double* err_out) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (n_sweeps < 0) return fail(c, PTYC_ERR_ARG, "n_sweeps must be >= 0");
+    if (n_sweeps == 0) return PTYC_OK;
+    // one error sum per sweep must fit beside the rest (checked before the
+    // schedules of all sweeps are built on the host)
+    if ((size_t)n_sweeps * sizeof(double) > kNoallocBytes / 4)
+        return fail(c, PTYC_ERR_ARG, "ptyc_sweep_noalloc: too many sweeps in one call for its work memory");
+    Plan p;
+    if ((rc = plan_sweeps(c, n_sweeps, order, order_len, off, n_batches, p)) != PTYC_OK) return rc;
+    unsigned char* base = (unsigned char*)noalloc_ptr(c->device);
+    if (!base) return fail(c, PTYC_ERR_STATE, "no work memory address for this device");
+    if (p.olen == 0) {
+        if (err_out)
+            for (int s = 0; s < n_sweeps; ++s) err_out[s] = 0.0;
+        c->sweeps_done += n_sweeps;
+        return PTYC_OK;
+    }
+    // layout of the work memory: one sweep's order entries, the spectrum
+    // exchange of the largest batch, its partial maxima of |S_j O|^2, the
+    // error partials of one sweep and one error sum per sweep
+    const size_t nn = (size_t)c->cfg.n * c->cfg.n;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_ent = 0;
+    const size_t o_exch = o_ent + up((size_t)p.olen * sizeof(OrderEntry));
+    const size_t o_wmax = o_exch + up((size_t)p.max_b * nn * sizeof(cf));
+    const size_t o_epart = o_wmax + up((size_t)p.max_b * c->st.row_blocks * sizeof(float));
+    const size_t o_esum = o_epart + up((size_t)p.olen * c->st.col_blocks * sizeof(double));
+    const size_t total = o_esum + up((size_t)n_sweeps * sizeof(double));
+    if (total > kNoallocBytes)
+        return fail(c, PTYC_ERR_ARG, "ptyc_sweep_noalloc needs " + std::to_string(total) +
+                                         " bytes of work memory; its limit is " + std::to_string(kNoallocBytes));
+    // an earlier pinned upload of ptyc_sweep may still be in flight
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    OrderEntry* d_ent = (OrderEntry*)(base + o_ent);
+    double* d_epart = (double*)(base + o_epart);
+    double* d_esum = (double*)(base + o_esum);
+    if ((rc = refresh_probe_max(c)) != PTYC_OK) return rc;
+    std::vector<OrderEntry> ents((size_t)p.olen);
+    for (int s = 0; s < n_sweeps; ++s) {
+        to_entries(c, p.orders[(size_t)s].data(), p.olen, ents.data());
+        // pageable source: the copy has read `ents` when the call returns,
+        // and it runs after the previous sweep's kernels on the stream
+        HIPCHK(c, hipMemcpyAsync(d_ent, ents.data(), (size_t)p.olen * sizeof(OrderEntry), hipMemcpyHostToDevice,
+                                 c->stream));
+        BatchArgs a = base_args(c);
+        a.order = d_ent;
+        a.scratch = (cf*)(base + o_exch);
+        a.winmax = (float*)(base + o_wmax);
+        a.err_part = d_epart;
+        const auto& f = p.offs[(size_t)s];
+        for (size_t b = 0; b + 1 < f.size(); ++b) {
+            a.off = f[b];
+            a.bsize = (int)(f[b + 1] - f[b]);
+            if (a.bsize == 0) continue;
+            a.pmax_in = pmax_half(c, c->pmax_cur);
+            a.pmax_out = pmax_half(c, c->pmax_cur ^ 1);
+            c->pmax_cur ^= 1;
+            HIPCHK(c, launch_batch(c->cfg.n, c->tile, a, c->stream));
+        }
+        if (err_out)
+            HIPCHK(c, launch_err_reduce(d_epart, p.olen * c->st.col_blocks, d_ent, p.olen,
+                                        (const double*)c->sum_i.p, d_esum + s, c->stream));
+    }
+    c->sweeps_done += n_sweeps;
+    if (err_out)
+        HIPCHK(c, hipMemcpyAsync(err_out, d_esum, (size_t)n_sweeps * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PTYC_OK;
 }
 

@@ -143,6 +143,19 @@ class Engine:
         _check(lib.ptyc_sweep(self._ctx, n_sweeps, op, olen, bp, nb, ep), self._ctx)
         return err
 
+    def sweep_noalloc(self, n_sweeps=1, order=None, batch_offsets=None, errors=False):
+        """sweep() through ptyc_sweep_noalloc: the same sweeps with the
+        library's fixed work memory (no allocation in the call)."""
+        lib = L.lib()
+        o, op = _i64(order)
+        b, bp = _i64(batch_offsets)
+        olen = 0 if o is None else len(o)
+        nb = 0 if b is None else len(b) - 1
+        err = np.zeros(n_sweeps, dtype=np.float64) if errors else None
+        ep = err.ctypes.data_as(C.POINTER(C.c_double)) if errors else None
+        _check(lib.ptyc_sweep_noalloc(self._ctx, n_sweeps, op, olen, bp, nb, ep), self._ctx)
+        return err
+
     def get_schedule(self):
         """(order, batch_offsets) of the next default sweep."""
         lib = L.lib()
