@@ -198,10 +198,9 @@ int ptyc_sweep_noalloc(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
 /* Run n_sweeps sweeps on each of n_ctx independent contexts together
  * (several scans of uneven size and pattern size at once).  Every context
  * follows its own default schedule, exactly as ptyc_sweep(ctx, n_sweeps,
- * NULL, ...) would, and produces the same bytes; a step advances every
- * unfinished context by one batch and launches each stage once for all
- * contexts of pattern size 64, 128 or 256 (and once per size for 16 and
- * 32), so small batches share the GPU.  All contexts
+ * NULL, ...) would, and produces the same bytes.  How the call is launched
+ * (one persistent kernel with per-scan barriers, or one batch of every
+ * scan per step) is described at ptyc_tune_multi below.  All contexts
  * must use the same device and stream; n_ctx <= PTYC_MULTI_MAX.  err_out:
  * NULL or n_ctx * n_sweeps doubles (context-major) receiving each sweep's
  * running Fourier error (this synchronises).  The call synchronises the
@@ -209,6 +208,35 @@ int ptyc_sweep_noalloc(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
  * repeated context, mixed streams, too many contexts). */
 #define PTYC_MULTI_MAX 64
 int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, double* err_out);
+
+/* How ptyc_sweep_multi runs, chosen per call by its first context.  Variants
+ * 0 .. ptyc_multi_variant_count()-1; all produce the same bytes.  With every
+ * context of pattern size 64, 128 or 256 the persistent variants (0-3) run
+ * the call as ONE persistent kernel: each scan is served by its own group
+ * of workgroups (sized in proportion to its work, capped at what its
+ * largest stage can use) and advances through its batches at its own pace,
+ * its three stages per batch separated by barriers over that group only;
+ * the variants differ in the inverse-stage tile at 64 and 128 px and in
+ * how workgroups are shared.  Variants 4-6 (and any call with a 16 or 32 px
+ * context) advance every scan by one batch per step with three launches
+ * per step for all scans together; 5 and 6 give scans whose largest batch
+ * holds at most 8 (16) positions an inverse-stage tile with fewer slots.
+ * The default is 6.  The launch form of the first context
+ * applies: PTYC_FORM_GRAPH replays the persistent launch as a HIP graph
+ * (rebuilt when the scan count or the grid changes), the other forms
+ * launch it cooperatively.  ptyc_tune_multi times every variant on `reps`
+ * runs of one joint sweep (each from the same state), keeps the fastest on
+ * the first context if it beats the current one by 2 %, restores every
+ * context's object, probe and sweep counter, and reports each variant's
+ * best time in ms_out (nullable, PTYC_MULTI_VARIANTS entries).  Errors:
+ * PTYC_ERR_ARG for a variant out of range, reps outside 1..100 or a bad
+ * context list; ptyc_get_multi_variant returns -1 for NULL. */
+#define PTYC_MULTI_VARIANTS 8
+int ptyc_multi_variant_count(void);
+int ptyc_set_multi_variant(ptyc_ctx* first, int variant);
+int ptyc_get_multi_variant(const ptyc_ctx* first);
+int ptyc_tune_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t reps, int32_t* variant_out,
+                    double* ms_out);
 
 /* Replace the object and the probe of each of n_ctx contexts by their mean
  * over the contexts (summed in list order).  This is the synchronisation
@@ -235,7 +263,10 @@ int ptyc_set_probe(ptyc_ctx* ctx, const void* in, int mem_kind);
 
 /* Launch form of a sweep: PTYC_FORM_BATCH (the default) launches three
  * kernels per batch; PTYC_FORM_PERSISTENT runs each sweep as one cooperative
- * kernel whose stages are separated by grid-wide barriers; PTYC_FORM_GRAPH
+ * kernel whose stages are separated by grid-wide barriers (in strict mode at
+ * pattern sizes up to 64: one workgroup that walks the whole order with the
+ * probe on chip, updating it after every position, the sequential ePIE of
+ * the paper's "ePIE Implementation"); PTYC_FORM_GRAPH
  * replays one instantiated HIP graph per sweep (the batch form's kernels as
  * a chain of nodes that read their batch extents from device memory; built
  * on the first sweep and again whenever the batch count grows, the largest
@@ -290,7 +321,8 @@ int ptyc_tune(ptyc_ctx* ctx, int32_t reps, int32_t* tile_out, double* ms_out);
 #define PTYC_KERNEL_ROWS_INV 2    /* inverse row FFTs, object step, batch probe step */
 #define PTYC_KERNEL_SWEEP 3       /* the persistent sweep kernel */
 #define PTYC_KERNEL_GRAPH 4       /* one replay of the sweep graph (graph form) */
-#define PTYC_KERNEL_KINDS 5
+#define PTYC_KERNEL_STRICT 5      /* the sequential one-workgroup sweep kernel */
+#define PTYC_KERNEL_KINDS 6
 int ptyc_profile(ptyc_ctx* ctx, int enable);
 int ptyc_profile_read(ptyc_ctx* ctx, int kind, double* total_ms, int64_t* launches,
                       int64_t* positions);

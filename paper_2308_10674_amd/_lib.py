@@ -23,12 +23,14 @@ PTYC_FORM_PERSISTENT = 2
 PTYC_FORM_GRAPH = 3
 PTYC_TILE_MAX = 8
 PTYC_NOALLOC_BYTES = 32 << 20
+PTYC_MULTI_VARIANTS = 8
 PTYC_KERNEL_ROWS_FWD = 0
 PTYC_KERNEL_COLS = 1
 PTYC_KERNEL_ROWS_INV = 2
 PTYC_KERNEL_SWEEP = 3
 PTYC_KERNEL_GRAPH = 4
-KERNEL_NAMES = {0: "k_rows_fwd", 1: "k_cols", 2: "k_rows_inv", 3: "k_sweep", 4: "sweep_graph"}
+PTYC_KERNEL_STRICT = 5
+KERNEL_NAMES = {0: "k_rows_fwd", 1: "k_cols", 2: "k_rows_inv", 3: "k_sweep", 4: "sweep_graph", 5: "k_strict"}
 PTYC_I_IS_SQRT = 1
 PTYC_I_CENTERED = 2
 
@@ -66,6 +68,10 @@ SIGNATURES = {
     "ptyc_sweep_noalloc": (C.c_int, [_P, C.c_int32, _I64P, C.c_int64, _I64P, C.c_int64, _DP]),
     "ptyc_sweep_multi": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP]),
     "ptyc_average": (C.c_int, [C.POINTER(_P), C.c_int32]),
+    "ptyc_multi_variant_count": (C.c_int, []),
+    "ptyc_set_multi_variant": (C.c_int, [_P, C.c_int]),
+    "ptyc_get_multi_variant": (C.c_int, [_P]),
+    "ptyc_tune_multi": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "ptyc_get_schedule": (C.c_int, [_P, _I64P, _I64P, _I64P]),
     "ptyc_set_ingest": (C.c_int, [_P, C.POINTER(Ingest)]),
     "ptyc_set_mask": (C.c_int, [_P, _P, C.c_int]),

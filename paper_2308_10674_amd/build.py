@@ -13,9 +13,11 @@ LIB = os.path.join(PKG, "libptyc.so")
 SOURCES = ["api.cpp", "schedule.cpp", "kernels.hip"]
 
 # Packed FP32 (v_pk_*_f32) is switched off for all device code; the compiler
-# would otherwise form those instructions from ordinary float code.
+# would otherwise form those instructions from ordinary float code.  No
+# floating-point contraction: the multiply-adds that fuse are written out as
+# fmaf in the source, so every kernel instantiation rounds identically.
 HIP_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]

@@ -60,6 +60,11 @@ struct DevBuf {
 
 }  // namespace
 
+// the default way a multi-context call runs (the stepped launches with the
+// eight-slot inverse tile for scans whose batches hold at most 16
+// positions; the fastest on the sixteen-scan workload, see kMultiVariants)
+constexpr int kMultiDefault = 6;
+
 struct ptyc_ctx {
     ptyc_config cfg{};
     hipStream_t stream = nullptr;
@@ -68,6 +73,7 @@ struct ptyc_ctx {
     std::string err;
     int form = kFormBatch;          // launch form of a sweep
     int capacity = 0;               // co-resident workgroups of the persistent kernel
+    int capacity_multi = 0;         // co-resident workgroups of the multi-scan persistent kernel (0: not yet asked)
     Shape sb{}, sp{}, sm{};         // work split of the per-batch (default tile), persistent and mixed-size launches
     int tile = 0;                   // tile variant of the per-batch kernels (batch and graph forms)
     Shape st{};                     // work split of that variant
@@ -87,6 +93,11 @@ struct ptyc_ctx {
     DevBuf bad;                      // int flag for ingest validation
     DevBuf sync;                     // [0] barrier counter, [1] barrier fault flag
     DevBuf multi;                    // batch descriptors of a multi-context call
+    DevBuf mbar;                     // arrival counters of the multi-scan persistent kernel (first context of a call)
+    int multi_variant = kMultiDefault; // how a multi-context call led by this context launches (kMultiVariants)
+    hipGraphExec_t mgexec = nullptr; // multi-scan persistent launch captured as a graph (graph form)
+    const void* mg_tab = nullptr;    // the descriptor table, count and grid the captured graph was built for
+    int mg_count = 0, mg_grid = 0;
     DevBuf mask;                     // uint8 [n][n] measured detector pixels (stored layout), if set
     ptyc_ingest ingest{};            // how raw frames become stored amplitudes
     DevBuf staging;                  // host intensities staged on the device
@@ -380,6 +391,7 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     c->col_blocks_max = std::max(c->sp.col_blocks, c->sm.col_blocks);
     for (int v = 0; v < tile_variants(cfg->n); ++v)
         c->col_blocks_max = std::max(c->col_blocks_max, shape_for(cfg->n, kFormBatch, v).col_blocks);
+    if (mixed_n(cfg->n)) c->col_blocks_max = std::max(c->col_blocks_max, multi_col_blocks(cfg->n));
     c->dev_limit = env_limit();
     c->colouring = new Colouring(cfg->n, max_batch_of(c));
     c->ingest.frame_h = c->ingest.frame_w = cfg->n;
@@ -436,8 +448,9 @@ void ptyc_destroy(ptyc_ctx* c) {
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
                       &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
                       &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging,
-                      &c->gorder, &c->goffs, &c->tune_save};
+                      &c->gorder, &c->goffs, &c->tune_save, &c->mbar};
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->mgexec) (void)hipGraphExecDestroy(c->mgexec);
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -910,6 +923,169 @@ int graph_sweep(ptyc_ctx* c, const Plan& p, int s) {
     return PTYC_OK;
 }
 
+// How a multi-context call runs.  persistent: one persistent kernel for all
+// scans (pattern sizes 64, 128, 256), each scan on its own group of
+// workgroups with its own barriers; inv64 / inv128: the inverse-stage tile
+// at 64 and 128 px; share: workgroups are given to scans in proportion to
+// (positions x N^2 log2 N)^share, capped at what a scan's largest stage can
+// use.  Otherwise every unfinished scan advances one batch per step, three
+// launches per step for all scans together, and a scan whose largest batch
+// holds at most `small` positions uses the eight-slot inverse tile.
+struct MultiVariant {
+    bool persistent;
+    int inv64, inv128;
+    double share;
+    int small;
+};
+constexpr MultiVariant kMultiVariants[] = {
+    {true, 0, 0, 1.0, 0},   {true, 1, 1, 1.0, 0},   {true, 1, 1, 0.5, 0}, {true, 0, 0, 0.5, 0},
+    {false, 0, 0, 1.0, 0},  {false, 0, 0, 1.0, 8},  {false, 0, 0, 1.0, 16},
+};
+constexpr int kMultiVariantCount = (int)(sizeof(kMultiVariants) / sizeof(kMultiVariants[0]));
+
+// Workgroups per scan: at least one each, the rest in proportion to the
+// weights, none beyond its cap, whatever a capped scan cannot use going to
+// the others (largest remainders first).  Returns the total given.
+int share_groups(const std::vector<double>& wt, const std::vector<int>& cap, int total, std::vector<int>& g) {
+    const size_t k = wt.size();
+    g.assign(k, 1);
+    int left = total - (int)k;
+    while (left > 0) {
+        double sw = 0.0;
+        for (size_t i = 0; i < k; ++i)
+            if (g[i] < cap[i]) sw += wt[i];
+        if (sw <= 0.0) break;
+        std::vector<std::pair<double, size_t>> frac;
+        int given = 0;
+        for (size_t i = 0; i < k; ++i) {
+            if (g[i] >= cap[i]) continue;
+            const double want = left * wt[i] / sw;
+            int add = std::min((int)want, cap[i] - g[i]);
+            g[i] += add;
+            given += add;
+            if (g[i] < cap[i]) frac.push_back({want - std::floor(want), i});
+        }
+        std::sort(frac.begin(), frac.end(), [](auto& x, auto& y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+        for (auto& f : frac) {
+            if (given >= left) break;
+            if (g[f.second] < cap[f.second]) {
+                ++g[f.second];
+                ++given;
+            }
+        }
+        if (given == 0) break;
+        left -= given;
+    }
+    int sum = 0;
+    for (int x : g) sum += x;
+    return sum;
+}
+
+// arrival counters of the multi-scan launch lie kBarStride counters (4 KiB)
+// apart: workgroups of different scans then poll different memory lines
+constexpr size_t kBarStride = 1024;
+
+// The persistent multi-scan launch.  Plans are staged (orders and offsets
+// of all sweeps on each context's device buffers, probe maxima refreshed).
+int multi_persistent(ptyc_ctx* const* ctxs, int n_ctx, int n_sweeps, double* err_out, const std::vector<Plan>& plans,
+                     const MultiVariant& mv) {
+    ptyc_ctx* c0 = ctxs[0];
+    std::vector<ScanArgs> sc;
+    std::vector<int> who, cap;
+    std::vector<double> wt;
+    for (int i = 0; i < n_ctx; ++i) {
+        const Plan& p = plans[(size_t)i];
+        if (p.olen == 0) continue;
+        ptyc_ctx* c = ctxs[i];
+        const int n = c->cfg.n;
+        ScanArgs x{};
+        x.a = base_args(c);
+        x.a.order = (const OrderEntry*)c->order.p;
+        x.offs = (const int64_t*)c->offs.p;
+        x.olen = p.olen;
+        x.nb = (int)p.nb;
+        x.n_sweeps = n_sweeps;
+        x.inv_tile = n == 64 ? mv.inv64 : n == 128 ? mv.inv128 : 0;
+        x.err = err_out ? (double*)c->err_dev.p : nullptr;
+        x.sum_i = (const double*)c->sum_i.p;
+        sc.push_back(x);
+        who.push_back(i);
+        cap.push_back(multi_need(n, (int)p.max_b, x.inv_tile));
+        wt.push_back(std::pow((double)p.olen * n * n * std::log2((double)n), mv.share));
+    }
+    if (c0->capacity_multi <= 0) c0->capacity_multi = multi_capacity();
+    if (sc.empty() || (int)sc.size() > c0->capacity_multi) return 1;   // nothing to run / not enough workgroups
+    std::vector<int> g;
+    const int grid = share_groups(wt, cap, c0->capacity_multi, g);
+    int g0 = 0;
+    int rc;
+    if ((rc = ensure(c0, c0->mbar, kMultiMax * kBarStride * sizeof(unsigned))) != PTYC_OK) return rc;
+    for (size_t k = 0; k < sc.size(); ++k) {
+        sc[k].g0 = g0;
+        sc[k].gn = g[k];
+        sc[k].bar = (unsigned*)c0->mbar.p + k * kBarStride;
+        g0 += g[k];
+    }
+    // the descriptor table may still be read by an earlier call's kernels
+    HIPCHK(c0, hipStreamSynchronize(c0->stream));
+    if ((rc = ensure(c0, c0->multi, sc.size() * sizeof(ScanArgs))) != PTYC_OK) return rc;
+    HIPCHK(c0, hipMemcpyAsync(c0->multi.p, sc.data(), sc.size() * sizeof(ScanArgs), hipMemcpyHostToDevice,
+                              c0->stream));
+    HIPCHK(c0, hipStreamSynchronize(c0->stream));
+    const ScanArgs* dev = (const ScanArgs*)c0->multi.p;
+    int* fault = (int*)((unsigned*)c0->sync.p + 1);
+    if (c0->form == kFormGraph) {
+        // the launch built as a graph once and replayed while the table, the
+        // scan count and the grid stay the same (the table's contents change
+        // from call to call; the kernels read them when they run)
+        if (!c0->mgexec || c0->mg_tab != (const void*)dev || c0->mg_count != (int)sc.size() || c0->mg_grid != grid) {
+            if (c0->mgexec) {
+                HIPCHK(c0, hipGraphExecDestroy(c0->mgexec));
+                c0->mgexec = nullptr;
+            }
+            hipGraph_t gr = nullptr;
+            HIPCHK(c0, build_multi_graph(dev, (int)sc.size(), grid, (unsigned*)c0->mbar.p,
+                                         (int)(sc.size() * kBarStride), fault, &gr));
+            const hipError_t ie = hipGraphInstantiate(&c0->mgexec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (ie != hipSuccess) {
+                c0->mgexec = nullptr;
+                return hip_fail(c0, ie, "hipGraphInstantiate");
+            }
+            c0->mg_tab = dev;
+            c0->mg_count = (int)sc.size();
+            c0->mg_grid = grid;
+        }
+        HIPCHK(c0, hipGraphLaunch(c0->mgexec, c0->stream));
+    } else {
+        HIPCHK(c0, launch_multi_persist(dev, (int)sc.size(), grid, (unsigned*)c0->mbar.p,
+                                        (int)(sc.size() * kBarStride), fault, true, c0->stream));
+    }
+    // each kernel swapped its scan's maxima halves after every non-empty batch
+    for (size_t k = 0; k < sc.size(); ++k) {
+        ptyc_ctx* c = ctxs[who[k]];
+        const Plan& p = plans[(size_t)who[k]];
+        int flips = 0;
+        for (int s = 0; s < n_sweeps; ++s)
+            for (size_t b = 0; b + 1 < p.offs[(size_t)s].size(); ++b) flips += p.offs[(size_t)s][b + 1] > p.offs[(size_t)s][b];
+        c->pmax_cur ^= flips & 1;
+    }
+    for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps_done += n_sweeps;
+    if (err_out) {
+        for (int i = 0; i < n_ctx; ++i) {
+            if (plans[(size_t)i].olen == 0) {
+                for (int s = 0; s < n_sweeps; ++s) err_out[(size_t)i * n_sweeps + s] = 0.0;
+                continue;
+            }
+            HIPCHK(c0, hipMemcpyAsync(err_out + (size_t)i * n_sweeps, ctxs[i]->err_dev.p,
+                                      (size_t)n_sweeps * sizeof(double), hipMemcpyDeviceToHost, c0->stream));
+        }
+        HIPCHK(c0, hipStreamSynchronize(c0->stream));
+        return check_fault(c0);
+    }
+    return PTYC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -933,19 +1109,38 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
     for (int s = 0; s < n_sweeps; ++s) {
         BatchArgs a = base_args(c);
         a.order = (const OrderEntry*)c->order.p + (size_t)s * olen;
-        if (c->form == kFormPersistent) {
-            SweepCtl ctl{};
-            ctl.offs = (const int64_t*)c->offs.p + (size_t)s * (nb + 1);
-            ctl.nb = (int)nb;
-            ctl.bar = (unsigned*)c->sync.p;
-            ctl.fault = (int*)((unsigned*)c->sync.p + 1);
-            ctl.nblocks = (unsigned)c->capacity;
+        if (c->form == kFormPersistent && c->cfg.mode == PTYC_MODE_STRICT && c->cfg.n <= kStrictMaxN) {
+            // sequential ePIE: one workgroup walks the whole order
             size_t e0 = 0;
             if (c->prof) {
                 if ((rc = take_events(c, 2, &e0)) != PTYC_OK) return rc;
                 HIPCHK(c, hipEventRecord(c->ev_pool[e0], c->stream));
             }
-            HIPCHK(c, launch_sweep(c->cfg.n, a, ctl, (int)p.max_b, c->stream));
+            a.off = 0;
+            HIPCHK(c, launch_strict(c->cfg.n, a, (int)olen, c->stream));
+            if (c->prof) {
+                HIPCHK(c, hipEventRecord(c->ev_pool[e0 + 1], c->stream));
+                c->marks.push_back({PTYC_KERNEL_STRICT, e0, e0 + 1, olen});
+            }
+            if ((rc = refresh_probe_max(c)) != PTYC_OK) return rc;
+            if (err_out && (rc = launch_sweep_error(c, p, s, 1)) != PTYC_OK) return rc;
+            continue;
+        } else if (c->form == kFormPersistent) {
+            ScanArgs sc{};
+            sc.a = a;
+            sc.offs = (const int64_t*)c->offs.p + (size_t)s * (nb + 1);
+            sc.olen = olen;
+            sc.nb = (int)nb;
+            sc.n_sweeps = 1;
+            sc.bar = (unsigned*)c->sync.p;
+            sc.sum_i = (const double*)c->sum_i.p;
+            size_t e0 = 0;
+            if (c->prof) {
+                if ((rc = take_events(c, 2, &e0)) != PTYC_OK) return rc;
+                HIPCHK(c, hipEventRecord(c->ev_pool[e0], c->stream));
+            }
+            HIPCHK(c, launch_sweep(c->cfg.n, sc, (int)p.max_b, c->capacity, (int*)((unsigned*)c->sync.p + 1),
+                                   c->stream));
             // the kernel swaps the maxima halves after every non-empty batch
             const auto& f = p.offs[(size_t)s];
             for (size_t b = 0; b + 1 < f.size(); ++b) c->pmax_cur ^= (f[b + 1] > f[b]) ? 1 : 0;
@@ -1086,6 +1281,13 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
     for (int i = 0; i < n_ctx; ++i)
         if (plans[(size_t)i].olen > 0 && (rc = stage_plan(ctxs[i], plans[(size_t)i], n_sweeps, kFormBatch)) != PTYC_OK)
             return rc;
+    const MultiVariant& mv = kMultiVariants[ctxs[0]->multi_variant];
+    bool persistent = mv.persistent;
+    for (int i = 0; i < n_ctx; ++i) persistent = persistent && mixed_n(ctxs[i]->cfg.n);
+    if (persistent) {
+        rc = multi_persistent(ctxs, n_ctx, n_sweeps, err_out, plans, mv);
+        if (rc <= 0) return rc;   // else: fewer workgroups than scans, or nothing to run; the stepped launches below
+    }
     // one step advances every unfinished context by one batch.  The pattern
     // sizes 64, 128 and 256 share three launches per step (mixed-size
     // kernels); 16 and 32 get three launches per size.  (Running the sizes
@@ -1114,6 +1316,7 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
                 const int s = (int)(k / p.nb);
                 const int64_t b = k % p.nb;
                 BatchArgs a = base_args(c);
+                a.itile = p.max_b <= mv.small ? 1 : 0;
                 c->pmax_cur ^= 1;   // this entry's inverse stage writes the other half
                 a.order = (const OrderEntry*)c->order.p + (size_t)s * p.olen;
                 a.off = p.offs[(size_t)s][(size_t)b];
@@ -1160,6 +1363,89 @@ int ptyc_sweep_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps, dou
         HIPCHK(c0, hipStreamSynchronize(c0->stream));
     }
     return PTYC_OK;
+}
+
+int ptyc_multi_variant_count(void) { return kMultiVariantCount; }
+
+int ptyc_set_multi_variant(ptyc_ctx* c, int v) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (v < 0 || v >= kMultiVariantCount) return fail(c, PTYC_ERR_ARG, "multi-context variant out of range");
+    c->multi_variant = v;
+    return PTYC_OK;
+}
+
+int ptyc_get_multi_variant(const ptyc_ctx* c) { return c ? c->multi_variant : -1; }
+
+int ptyc_tune_multi(ptyc_ctx* const* ctxs, int32_t n_ctx, int32_t reps, int32_t* variant_out, double* ms_out) {
+    if (!ctxs || n_ctx <= 0 || n_ctx > PTYC_MULTI_MAX) return PTYC_ERR_ARG;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return PTYC_ERR_ARG;
+        int rc = usable(ctxs[i]);
+        if (rc) return rc;
+    }
+    ptyc_ctx* c0 = ctxs[0];
+    if (reps < 1 || reps > 100) return fail(c0, PTYC_ERR_ARG, "reps must be in 1..100");
+    if (ms_out)
+        for (int v = 0; v < PTYC_MULTI_VARIANTS; ++v) ms_out[v] = 0.0;
+    int rc;
+    // the state a sweep changes: object, probe (and its maxima), sweep counter
+    std::vector<int64_t> done0((size_t)n_ctx);
+    for (int i = 0; i < n_ctx; ++i) {
+        ptyc_ctx* c = ctxs[i];
+        const size_t ob = (size_t)c->cfg.h * c->cfg.w * sizeof(cf), pb = (size_t)c->cfg.n * c->cfg.n * sizeof(cf);
+        if ((rc = ensure(c, c->tune_save, ob + pb)) != PTYC_OK) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->tune_save.p, c->obj.p, ob, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync((char*)c->tune_save.p + ob, c->probe.p, pb, hipMemcpyDeviceToDevice, c->stream));
+        done0[(size_t)i] = c->sweeps_done;
+    }
+    auto restore = [&]() -> int {
+        for (int i = 0; i < n_ctx; ++i) {
+            ptyc_ctx* c = ctxs[i];
+            const size_t ob = (size_t)c->cfg.h * c->cfg.w * sizeof(cf), pb = (size_t)c->cfg.n * c->cfg.n * sizeof(cf);
+            HIPCHK(c, hipMemcpyAsync(c->obj.p, c->tune_save.p, ob, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->probe.p, (char*)c->tune_save.p + ob, pb, hipMemcpyDeviceToDevice, c->stream));
+            c->sweeps_done = done0[(size_t)i];
+            int r = refresh_probe_max(c);
+            if (r != PTYC_OK) return r;
+        }
+        return PTYC_OK;
+    };
+    const int v0 = c0->multi_variant;
+    std::vector<double> times((size_t)kMultiVariantCount, 0.0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    rc = he == hipSuccess ? PTYC_OK : hip_fail(c0, he, "hipEventCreate");
+    for (int v = 0; v < kMultiVariantCount && rc == PTYC_OK; ++v) {
+        c0->multi_variant = v;
+        for (int r = 0; r < reps && rc == PTYC_OK; ++r) {
+            if ((rc = restore()) != PTYC_OK) break;
+            if ((he = hipEventRecord(e0, c0->stream)) != hipSuccess) { rc = hip_fail(c0, he, "hipEventRecord"); break; }
+            if ((rc = ptyc_sweep_multi(ctxs, n_ctx, 1, nullptr)) != PTYC_OK) break;
+            if ((he = hipEventRecord(e1, c0->stream)) != hipSuccess) { rc = hip_fail(c0, he, "hipEventRecord"); break; }
+            if ((he = hipEventSynchronize(e1)) != hipSuccess) { rc = hip_fail(c0, he, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_fail(c0, he, "hipEventElapsedTime"); break; }
+            if (r == 0 || ms < times[(size_t)v]) times[(size_t)v] = ms;
+        }
+        if (rc == PTYC_OK && ms_out && v < PTYC_MULTI_VARIANTS) ms_out[v] = times[(size_t)v];
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    int best = v0;
+    if (rc == PTYC_OK) {
+        for (int v = 0; v < kMultiVariantCount; ++v)
+            if (times[(size_t)v] < times[(size_t)best] * (1.0 - kTuneMargin)) best = v;
+    }
+    for (int i = 0; i < n_ctx; ++i)
+        if (ctxs[i]->poisoned) return rc != PTYC_OK ? rc : PTYC_ERR_HIP;
+    c0->multi_variant = best;
+    const int rc2 = restore();
+    if (rc == PTYC_OK) rc = rc2;
+    if (rc == PTYC_OK) HIPCHK(c0, hipStreamSynchronize(c0->stream));
+    if (variant_out) *variant_out = c0->multi_variant;
+    return rc;
 }
 
 int ptyc_get_object(ptyc_ctx* c, void* out, int kind) {

@@ -23,14 +23,21 @@ __host__ __device__ inline cf mk(float x, float y) { return cf{x, y}; }
 __host__ __device__ inline cf operator+(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
 __host__ __device__ inline cf operator-(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
 __host__ __device__ inline cf operator*(float s, cf a) { return cf{s * a.x, s * a.y}; }
+// The library is compiled without floating-point contraction, so which
+// multiplications fuse with an addition is fixed here, in the source, and
+// every kernel that uses these helpers rounds the same way whatever code
+// surrounds them (the launch forms and tile variants give the same bits).
+__host__ __device__ inline float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __host__ __device__ inline cf cmul(cf a, cf b) {
-    return cf{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return cf{fma_(a.x, b.x, -(a.y * b.y)), fma_(a.x, b.y, a.y * b.x)};
 }
 // conj(a) * b
 __host__ __device__ inline cf cmulc(cf a, cf b) {
-    return cf{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+    return cf{fma_(a.x, b.x, a.y * b.y), fma_(a.x, b.y, -(a.y * b.x))};
 }
-__host__ __device__ inline float norm2(cf a) { return a.x * a.x + a.y * a.y; }
+// y + s x
+__host__ __device__ inline cf axpy(float s, cf x, cf y) { return cf{fma_(s, x.x, y.x), fma_(s, x.y, y.y)}; }
+__host__ __device__ inline float norm2(cf a) { return fma_(a.x, a.x, a.y * a.y); }
 
 // multiply by DIR*i (DIR = -1 forward, +1 inverse): W_4^1 of that direction
 template <int DIR>
@@ -42,7 +49,7 @@ __host__ __device__ inline cf rot(cf v) {
 template <int DIR>
 __host__ __device__ inline cf twc(cf v, float c, float s) {
     const float sd = DIR < 0 ? -s : s;
-    return cf{v.x * c - v.y * sd, v.x * sd + v.y * c};
+    return cf{fma_(v.x, c, -(v.y * sd)), fma_(v.x, sd, v.y * c)};
 }
 
 // cos and sin of pi/8 and pi/4 (mathematical constants)

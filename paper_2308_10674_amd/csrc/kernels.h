@@ -43,6 +43,7 @@ struct BatchArgs {
     const int64_t* boffs;     // graph nodes: off and bsize are read from boffs[batch], boffs[batch + 1]
     int batch;
     int n;                    // pattern size (read by the mixed-size kernels)
+    int itile;                // mixed-size inverse stage: 0 the default tile, 1 the eight-slot tile
 };
 
 // How raw detector frames become stored amplitudes.
@@ -69,13 +70,19 @@ struct Shape {
     int probe_blocks; // pmax entries (per-wave partials)
 };
 
-// Controls of the persistent sweep kernel.
-struct SweepCtl {
-    const int64_t* offs;  // [nb + 1] batch offsets into the order (device)
-    int nb;
-    unsigned* bar;        // arrival counter, zeroed by the launch
-    int* fault;           // raised when a barrier wait exceeds its bound
-    unsigned nblocks;     // in: co-resident capacity; the launch uses min(need, capacity)
+// One scan as a persistent kernel runs it: every batch of n_sweeps sweeps.
+struct ScanArgs {
+    BatchArgs a;              // the scan's buffers; a.order holds the n_sweeps orders, olen entries each;
+                              // a.pmax_in / a.pmax_out: the probe maxima halves at the start
+    const int64_t* offs;      // [n_sweeps][nb + 1] batch offsets into each sweep's order (device)
+    int64_t olen;             // positions per sweep
+    int nb;                   // batches per sweep
+    int n_sweeps;
+    int g0, gn;               // workgroups g0 .. g0 + gn - 1 of the launch serve this scan
+    int inv_tile;             // inverse-stage tile of the multi-scan kernel (0 or 1)
+    unsigned* bar;            // arrival counter of those workgroups, zero at the launch
+    double* err;              // nullptr, or [n_sweeps] running Fourier error of each sweep (multi-scan kernel)
+    const double* sum_i;      // [positions] sum of I per position (the error's denominator)
 };
 
 bool supported_n(int n);
@@ -100,10 +107,36 @@ bool mixed_n(int n);
 hipError_t launch_batch_mixed(const BatchArgs* dev_tab, const BatchArgs* host_tab, int count, hipStream_t s);
 hipError_t launch_batch_multi(int n, const BatchArgs* dev_tab, const BatchArgs* host_tab, int count,
                               hipStream_t s);
+// Sequential ePIE of `count` positions a.order[a.off ..] in one workgroup
+// (pattern sizes up to kStrictMaxN): the probe stays on chip and is updated
+// after every position; one error partial per position at
+// a.err_part[a.off + k]; a.probe holds the final probe afterwards (its
+// partial maxima are not refreshed).
+constexpr int kStrictMaxN = 64;
+hipError_t launch_strict(int n, const BatchArgs& a, int count, hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel
-// The persistent sweep swaps a.pmax_in and a.pmax_out after every non-empty
-// batch.
-hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s);
+// One scan's sweeps as one cooperative launch of at most `capacity`
+// workgroups (the persistent form); the counter sc.bar is zeroed first.
+// The kernel swaps the probe maxima halves after every non-empty batch.
+hipError_t launch_sweep(int n, const ScanArgs& sc, int max_batch, int capacity, int* fault, hipStream_t s);
+// Several scans (pattern sizes 64, 128, 256) as one persistent launch of
+// `grid` workgroups: dev_scans[i] on the device (the same descriptors as
+// host_scans, whose g0 / gn tile 0 .. grid - 1 in ascending order), their
+// arrival counters inside the n_bars counters at bars (all zeroed first by
+// a kernel).  coop: a
+// cooperative launch (grid must not exceed multi_capacity()); otherwise a
+// plain launch, which stream capture accepts.
+int multi_capacity();
+// workgroups a scan of pattern size n can keep busy in its largest stage
+int multi_need(int n, int max_batch, int inv_tile);
+// error partials per position of the multi-scan kernel at pattern size n
+int multi_col_blocks(int n);
+hipError_t launch_multi_persist(const ScanArgs* dev_scans, int count, int grid, unsigned* bars, int n_bars, int* fault,
+                                bool coop, hipStream_t s);
+// the same launch (counter reset, then the persistent kernel as a plain
+// launch of `grid` workgroups) as a two-node graph
+hipError_t build_multi_graph(const ScanArgs* dev_scans, int count, int grid, unsigned* bars, int n_bars, int* fault,
+                             hipGraph_t* out);
 // One sweep of nb batches as a graph of 3 nb kernel nodes in a chain.  The
 // nodes read their batch's offset and size from a.boffs (a.boffs[b] ..
 // a.boffs[b + 1] in a.order) when they run, and their grids cover max_b

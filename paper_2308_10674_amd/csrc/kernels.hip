@@ -69,12 +69,13 @@ __device__ __forceinline__ double lane_of(double v, int lane) {
 // a group gets the group's result
 template <int G>
 __device__ inline float group_max(float v) {
-    static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
+    static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group size");
     v = fmaxf(v, dpp<kDppQuadXor1>(v));
     if constexpr (G >= 4) v = fmaxf(v, dpp<kDppQuadXor2>(v));
     if constexpr (G >= 8) v = fmaxf(v, dpp<kDppRowHalfMirror>(v));
     if constexpr (G >= 16) v = fmaxf(v, dpp<kDppRowMirror>(v));
-    if constexpr (G == 32) v = fmaxf(v, __shfl_xor(v, 16, kWave));
+    if constexpr (G >= 32) v = fmaxf(v, __shfl_xor(v, 16, kWave));
+    if constexpr (G == 64) v = fmaxf(v, __shfl_xor(v, 32, kWave));
     return v;
 }
 
@@ -246,11 +247,58 @@ __device__ __forceinline__ void store_through(cf* p, cf v) {
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Access to data that another workgroup of the same kernel writes.  In the
+// per-batch kernels (COH = false) a kernel boundary separates producer and
+// consumer, so plain loads are coherent; only the bulk stores are written
+// through (above).  The persistent kernels (COH = true) have no kernel
+// boundary between stages: every such load is a device-scope relaxed load
+// (it misses the caches that may hold a stale line) and every such store a
+// device-scope relaxed store (written through), so their barriers need no
+// cache write-back or invalidation, only the wait for their own stores.
+template <bool COH>
+__device__ __forceinline__ cf ldc(const cf* p) {
+    if constexpr (COH) {
+        const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cf v;
+        __builtin_memcpy(&v, &b, sizeof(v));
+        return v;
+    } else {
+        return *p;
+    }
+}
+template <bool COH>
+__device__ __forceinline__ float ldc(const float* p) {
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ double ldc(const double* p) {
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+// a store of a small result (probe, partial maxima, error partials)
+template <bool COH>
+__device__ __forceinline__ void stc(cf* p, cf v) {
+    if constexpr (COH) store_through(p, v);
+    else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void stc(float* p, float v) {
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void stc(double* p, double v) {
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
 // ---------------------------------------------------------------- stage 1
 // psi = P * S_j O for rows rb*RB .. rb*RB+RB-1 of slot `slot`, 1D FFT of
 // each row, spectrum rows to scratch; partial max |S_j O|^2 to winmax, one
 // entry per wave (no workgroup barrier: a maximum is exact in any order).
-template <int N, int RB>
+template <int N, int RB, bool COH = false>
 __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int rb, cf* lds) {
     using g = RowG<N, RB>;
     const int t = threadIdx.x % g::T, rl = threadIdx.x / g::T;
@@ -265,9 +313,9 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
 #pragma unroll
     for (int n1 = 0; n1 < g::N1; ++n1) {
         const int col = g::N2 * n1 + t;
-        const cf o = orow[col];
+        const cf o = ldc<COH>(&orow[col]);
         m = fmaxf(m, norm2(o));
-        v[n1] = cmul(prow[col], o);
+        v[n1] = cmul(ldc<COH>(&prow[col]), o);
     }
     cf* z = lds + rl * Lds<N>::LINE;
     passA_to_lds<N, -1>(v, z, t, w);
@@ -277,13 +325,14 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
 #pragma unroll
     for (int i = 0; i < g::N1; ++i) store_through(&srow[Fact<N>::out(t, i)], v[i]);
     m = wave_max(m);
-    if (threadIdx.x % kWave == 0) a.winmax[slot * kWinParts<N> + rb * (g::NT / kWave) + threadIdx.x / kWave] = m;
+    if (threadIdx.x % kWave == 0)
+        stc<COH>(&a.winmax[slot * kWinParts<N> + rb * (g::NT / kWave) + threadIdx.x / kWave], m);
 }
 
 // ---------------------------------------------------------------- stage 2
 // Columns cb*CB .. of slot `slot`: 1D FFT, Psi' = sqrt(I_j) sgn(Psi) with
 // the error partial, inverse 1D FFT (unscaled), back to scratch.
-template <int N, int CB, int MODE = kModeEpie>
+template <int N, int CB, int MODE = kModeEpie, bool COH = false>
 __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds,
                                            double* red) {
     using g = ColG<N, CB>;
@@ -299,7 +348,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
     cf v[g::N1];
     float amp[g::N1];
 #pragma unroll
-    for (int n1 = 0; n1 < g::N1; ++n1) v[n1] = base[(size_t)(g::N2 * n1 + t) * N];
+    for (int n1 = 0; n1 < g::N1; ++n1) v[n1] = ldc<COH>(&base[(size_t)(g::N2 * n1 + t) * N]);
     bool valid[g::N1];
 #pragma unroll
     for (int i = 0; i < g::N1; ++i) {
@@ -345,7 +394,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
         for (int n1 = 0; n1 < g::N1; ++n1) store_through(&base[(size_t)(g::N2 * n1 + t) * N], v[n1]);
     }
     const double tot = block_sum<g::NT>((double)e, red);
-    if (threadIdx.x == 0) a.err_part[(a.off + slot) * g::GC + cb] = tot;
+    if (threadIdx.x == 0) stc<COH>(&a.err_part[(a.off + slot) * g::GC + cb], tot);
 }
 
 // ---------------------------------------------------------------- stage 3
@@ -355,7 +404,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 // conj(S_j O) Delta / max|S_j O|^2 summed over slots in slot order, then
 // P_{b+1} written for the block.  bsize == 0 only refreshes the block's
 // max |P|^2.
-template <int N, int R, int S, int MODE = kModeEpie>
+template <int N, int R, int S, int MODE = kModeEpie, bool COH = false>
 __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl) {
     using g = InvG<N, R, S>;
     const int t = threadIdx.x % g::T;
@@ -366,13 +415,13 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     const bool owner = threadIdx.x < g::R * N;
     const int own_rl = owner ? threadIdx.x / N : 0, own_c = threadIdx.x % N;
     const size_t own = (size_t)(rb * g::R + own_rl) * N + own_c;
-    const cf p_own = owner ? (MODE == kModeEpie ? a.probe[own] : a.gprobe[own]) : cf{0.f, 0.f};
+    const cf p_own = owner ? (MODE == kModeEpie ? ldc<COH>(&a.probe[own]) : a.gprobe[own]) : cf{0.f, 0.f};
     cf acc = cf{0.f, 0.f};
     if (a.bsize > 0) {
         const cf* prow = a.probe + (size_t)r * N;
         cf p[g::N1];
 #pragma unroll
-        for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = prow[g::N2 * n1 + t];
+        for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = ldc<COH>(&prow[g::N2 * n1 + t]);
         float ostep = 0.f;
         if (MODE == kModeEpie) {
             // every wave reduces all partial maxima itself (no barrier)
@@ -380,7 +429,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
 #pragma unroll
             for (int k = 0; k < (kProbeParts<N> + kWave - 1) / kWave; ++k) {
                 const int i = k * kWave + (int)(threadIdx.x % kWave);
-                if (i < kProbeParts<N>) pm = fmaxf(pm, a.pmax_in[i]);
+                if (i < kProbeParts<N>) pm = fmaxf(pm, ldc<COH>(&a.pmax_in[i]));
             }
             pm = wave_max(pm);
             ostep = a.alpha / pm;
@@ -402,9 +451,9 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 const cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
                 orow = a.obj + (size_t)(e.row + r) * a.w + e.col;
 #pragma unroll
-                for (int i = 0; i < g::N1; ++i) v[i] = srow[Fact<N>::out(t, i)];
+                for (int i = 0; i < g::N1; ++i) v[i] = ldc<COH>(&srow[Fact<N>::out(t, i)]);
 #pragma unroll
-                for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = orow[g::N2 * n1 + t];
+                for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = ldc<COH>(&orow[g::N2 * n1 + t]);
             } else {
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
@@ -424,7 +473,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
 #pragma unroll
             for (int k = 0; k < kWm; ++k) {
                 const int i = k * GT + (int)(threadIdx.x % GT);
-                wpart[k] = MODE == kModeEpie && i < kWinParts<N> ? a.winmax[ws * kWinParts<N> + i] : 0.f;
+                wpart[k] = MODE == kModeEpie && i < kWinParts<N> ? ldc<COH>(&a.winmax[ws * kWinParts<N> + i]) : 0.f;
             }
             passBinv_to_lds<N, +1, 1>(v, z, t, wb);
             __syncthreads();
@@ -443,7 +492,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     const int col = g::N2 * n1 + t;
                     const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
-                    store_through(&orow[col], o[n1] + ostep * cmulc(p[n1], delta));
+                    store_through(&orow[col], axpy(ostep, cmulc(p[n1], delta), o[n1]));
                     drow[col] = pstep * cmulc(o[n1], delta);
                 }
             } else if (act) {
@@ -479,13 +528,13 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     if (MODE == kModeEpie) {
         cf pn = p_own;
         if (a.bsize > 0 && owner) {
-            pn = p_own + (a.beta / (float)a.bsize) * acc;
-            a.probe[own] = pn;
+            pn = axpy(a.beta / (float)a.bsize, acc, p_own);
+            stc<COH>(&a.probe[own], pn);
         }
         // one partial per wave that owns probe elements (waves past R*N own none)
         const float m = wave_max(norm2(pn));
         if (threadIdx.x % kWave == 0 && threadIdx.x < g::R * N)
-            a.pmax_out[rb * (g::R * N / kWave) + threadIdx.x / kWave] = m;
+            stc<COH>(&a.pmax_out[rb * (g::R * N / kWave) + threadIdx.x / kWave], m);
     } else if (a.bsize > 0 && owner) {
         a.gprobe[own] = p_own + acc;
     }
@@ -597,10 +646,14 @@ __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
 // of any element, and the partial-maximum layouts do not depend on the
 // tile: the results equal those of the per-size kernels.
 constexpr int kMixRowNT = 256, kMixInvNT = 512;
+// The inverse stage has a second tile with fewer slots (S2, R2 rows each)
+// for scans whose batches are small (spiral scans: a handful of positions
+// per batch), so fewer lanes transform idle slots; BatchArgs::itile selects
+// it.
 template <int N> struct MixTile;
-template <> struct MixTile<64>  { static constexpr int RB = 32, R = 4, S = 16; };
-template <> struct MixTile<128> { static constexpr int RB = 16, R = 1, S = 32; };
-template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32; };
+template <> struct MixTile<64>  { static constexpr int RB = 32, R = 4, S = 16, R2 = 8, S2 = 8; };
+template <> struct MixTile<128> { static constexpr int RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
+template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32, R2 = 2, S2 = 16; };
 template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
 template <int N> constexpr int kMixInvLds = MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE;
 template <int N> constexpr int kMixInvDl = MixTile<N>::S * MixTile<N>::R * N;
@@ -626,8 +679,13 @@ __device__ __forceinline__ void mix_cols(const BatchArgs& a, int local, cf* lds,
 template <int N>
 __device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* lds, cf* dl) {
     using g = InvG<N, MixTile<N>::R, MixTile<N>::S>;
-    static_assert(g::NT == kMixInvNT, "mixed inverse tile");
-    stage_rows_inv<N, g::R, g::S>(a, local, lds, dl);
+    using g2 = InvG<N, MixTile<N>::R2, MixTile<N>::S2>;
+    static_assert(g::NT == kMixInvNT && g2::NT == kMixInvNT, "mixed inverse tile");
+    static_assert(g2::S * g2::R <= g::S * g::R, "the small-batch tile fits the LDS of the default one");
+    if (a.itile)
+        stage_rows_inv<N, g2::R, g2::S>(a, local, lds, dl);
+    else
+        stage_rows_inv<N, g::R, g::S>(a, local, lds, dl);
 }
 
 __global__ __launch_bounds__(kMixRowNT) void k_rows_fwd_mix(MultiArgs m) {
@@ -710,40 +768,109 @@ __global__ __launch_bounds__(256) void k_fill_zero(cf* p, int64_t n) {
         p[i] = cf{0.f, 0.f};
 }
 
-// ---------------------------------------------------------------- persistent sweep
-// One cooperative launch runs every batch of a sweep.  Stages are separated
-// by grid-wide barriers: a monotone arrival counter at agent scope (release
-// before the arrival, acquire after the wait).  Every wait is bounded; on
-// expiry the fault flag is raised and all workgroups leave, so the grid
-// always drains.
+// ---------------------------------------------------------------- persistent sweeps
+// A persistent kernel runs every batch of one or more sweeps of a scan with
+// a fixed set of co-resident workgroups.  The stages of a batch are
+// separated by barriers over the workgroups that serve that scan: a
+// monotone arrival counter (zeroed before the launch) that each workgroup
+// increments once its own device-coherent stores have completed, then
+// polls until every workgroup of the scan has arrived.  All data the stages
+// pass between workgroups goes through the coherent accesses (COH = true),
+// so no cache write-back or invalidation is needed.  Every wait is bounded;
+// on expiry the fault flag is raised and the waiting workgroups leave, so
+// the grid always drains.
 constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ inline bool grid_barrier(const SweepCtl& c, unsigned epoch, int* ok_sh) {
+__device__ inline bool group_barrier(unsigned* bar, unsigned target, int* fault, int* ok_sh) {
+    // this wave's stores have completed (the coherent ones are written
+    // through); the memory clobber keeps the compiler from moving memory
+    // accesses across the wait
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = epoch * c.nblocks;
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 1023u) == 0u &&
-                (spins > kSpinLimit || __hip_atomic_load(c.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                __hip_atomic_store(c.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                (spins > kSpinLimit || __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *ok_sh = ok;
     }
     __syncthreads();
+    asm volatile("" ::: "memory");
     return *ok_sh != 0;
 }
 
+// Running Fourier error of one sweep from its error partials: the same
+// summation order as k_err_reduce (256 threads, strided, then block_sum),
+// so the value is the one the per-batch launches report.
+__device__ inline void sweep_error(const double* err_part, int64_t n_part, const OrderEntry* order,
+                                   int64_t order_len, const double* sum_i, double* out, double* red) {
+    double num = 0.0, den = 0.0;
+    for (int64_t i = threadIdx.x; i < n_part; i += 256) num += ldc<true>(&err_part[i]);
+    for (int64_t i = threadIdx.x; i < order_len; i += 256) den += sum_i[order[i].j];
+    num = block_sum<256>(num, red);
+    den = block_sum<256>(den, red);
+    if (threadIdx.x == 0) *out = den > 0.0 ? num / den : 0.0;
+}
+
+// The sweeps of one scan by workgroup `local` of the sc.gn that serve it:
+// for every non-empty batch the forward row items, the column items and
+// the inverse row items are dealt round-robin to the scan's workgroups,
+// with a barrier after each stage; the probe maxima alternate halves after
+// every non-empty batch.  ERR: the workgroup with local index 0 reduces
+// each sweep's error after its last batch (256 threads).
+template <int N, int RB, int CB, int IR, int IS, bool ERR>
+__device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds, cf* dl, double* red,
+                             int* ok_sh) {
+    using rg = RowG<N, RB>;
+    using cg = ColG<N, CB>;
+    using ig = InvG<N, IR, IS>;
+    BatchArgs a = sc.a;
+    unsigned target = 0;
+    for (int sw = 0; sw < sc.n_sweeps; ++sw) {
+        a.order = sc.a.order + (size_t)sw * sc.olen;
+        const int64_t* offs = sc.offs + (size_t)sw * (sc.nb + 1);
+        for (int b = 0; b < sc.nb; ++b) {
+            const int64_t off = offs[b];
+            const int bs = (int)(offs[b + 1] - off);
+            if (bs <= 0) continue;
+            a.off = off;
+            a.bsize = bs;
+            for (int it = local; it < bs * rg::G; it += sc.gn)
+                stage_rows_fwd<N, RB, true>(a, it / rg::G, it % rg::G, lds);
+            target += (unsigned)sc.gn;
+            if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
+            for (int it = local; it < bs * cg::GC; it += sc.gn)
+                stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds, red);
+            target += (unsigned)sc.gn;
+            if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
+            for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, kModeEpie, true>(a, it, lds, dl);
+            target += (unsigned)sc.gn;
+            if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
+            // the maxima just written are those of the next batch's probe
+            float* const next_in = a.pmax_out;
+            a.pmax_out = const_cast<float*>(a.pmax_in);
+            a.pmax_in = next_in;
+        }
+        if constexpr (ERR) {
+            // the next sweep overwrites the partials only after its first
+            // barrier, which this workgroup reaches after the reduction
+            if (sc.err && local == 0) sweep_error(a.err_part, sc.olen * cg::GC, a.order, sc.olen, sc.sum_i,
+                                                  sc.err + sw, red);
+        }
+    }
+}
+
+// One scan, every workgroup of the launch (the "persistent" launch form).
 template <int N>
-__global__ __launch_bounds__(kSweepNT<N>) void k_sweep(BatchArgs a, SweepCtl c) {
+__global__ __launch_bounds__(kSweepNT<N>) void k_sweep(ScanArgs sc, int* fault) {
     constexpr int TB = PTile<N>::B;
     using rg = RowG<N, TB>;
     using cg = ColG<N, TB>;
@@ -755,30 +882,230 @@ __global__ __launch_bounds__(kSweepNT<N>) void k_sweep(BatchArgs a, SweepCtl c) 
     __shared__ cf dl[ig::S * ig::R * N];
     __shared__ double redd[NT / kWave];
     __shared__ int ok_sh;
-    unsigned epoch = 0;
-    for (int b = 0; b < c.nb; ++b) {
-        const int64_t off = c.offs[b];
-        const int bs = (int)(c.offs[b + 1] - off);
-        if (bs <= 0) continue;
-        a.off = off;
-        a.bsize = bs;
-        for (int it = blockIdx.x; it < bs * rg::G; it += gridDim.x)
-            stage_rows_fwd<N, TB>(a, it / rg::G, it % rg::G, lds);
-        if (!grid_barrier(c, ++epoch, &ok_sh)) return;
-        for (int it = blockIdx.x; it < bs * cg::GC; it += gridDim.x)
-            stage_cols<N, TB>(a, it / cg::GC, it % cg::GC, lds, redd);
-        if (!grid_barrier(c, ++epoch, &ok_sh)) return;
-        for (int it = blockIdx.x; it < ig::GI; it += gridDim.x)
-            stage_rows_inv<N, ig::R, ig::S>(a, it, lds, dl);
-        if (!grid_barrier(c, ++epoch, &ok_sh)) return;
-        // the maxima just written are those of the next batch's probe
-        float* const next_in = a.pmax_out;
-        a.pmax_out = const_cast<float*>(a.pmax_in);
-        a.pmax_in = next_in;
+    sc.gn = (int)gridDim.x;
+    persist_scan<N, TB, TB, ig::R, ig::S, false>(sc, (int)blockIdx.x, fault, lds, dl, redd, &ok_sh);
+}
+
+// Several independent scans in one launch (pattern sizes 64, 128, 256):
+// workgroups sc.g0 .. sc.g0 + sc.gn - 1 serve scan sc, each scan advancing
+// through its own batches at its own pace (its barriers count only its own
+// workgroups).  One workgroup size (kMP threads) for every size and stage;
+// the tiles group rows, columns and slots differently from the per-batch
+// kernels but compute every element the same way, so each scan's object
+// and probe equal those of its own per-batch sweeps bit for bit.
+constexpr int kMP = 256;
+template <int N> struct MPTile;
+template <> struct MPTile<64>  { static constexpr int RB = 32, CB = 32, R0 = 4, S0 = 8, R1 = 2, S1 = 16; };
+template <> struct MPTile<128> { static constexpr int RB = 16, CB = 16, R0 = 1, S0 = 16, R1 = 2, S1 = 8; };
+template <> struct MPTile<256> { static constexpr int RB = 16, CB = 16, R0 = 1, S0 = 16, R1 = 1, S1 = 16; };
+template <int N> constexpr int kMPLines =
+    cmax3(MPTile<N>::RB, MPTile<N>::S0 * MPTile<N>::R0, MPTile<N>::S1 * MPTile<N>::R1) * Lds<N>::LINE;
+template <int N> constexpr int kMPDl = cmax3(MPTile<N>::S0 * MPTile<N>::R0, MPTile<N>::S1 * MPTile<N>::R1, 0) * N;
+constexpr int kMPLds = cmax3(kMPLines<64>, kMPLines<128>, kMPLines<256>);
+constexpr int kMPDlMax = cmax3(kMPDl<64>, kMPDl<128>, kMPDl<256>);
+
+template <int N>
+__device__ __forceinline__ void multi_scan(const ScanArgs& sc, int local, int* fault, cf* lds, cf* dl, double* red,
+                                           int* ok_sh) {
+    using t = MPTile<N>;
+    static_assert(RowG<N, t::RB>::NT == kMP && ColG<N, t::CB>::NT == kMP, "multi-scan row and column tiles");
+    static_assert(InvG<N, t::R0, t::S0>::NT == kMP && InvG<N, t::R1, t::S1>::NT == kMP, "multi-scan inverse tiles");
+    if (sc.inv_tile == 0)
+        persist_scan<N, t::RB, t::CB, t::R0, t::S0, true>(sc, local, fault, lds, dl, red, ok_sh);
+    else
+        persist_scan<N, t::RB, t::CB, t::R1, t::S1, true>(sc, local, fault, lds, dl, red, ok_sh);
+}
+
+__global__ __launch_bounds__(kMP) void k_multi_persist(const ScanArgs* scans, int count, int* fault) {
+    __shared__ cf lds[kMPLds];
+    __shared__ cf dl[kMPDlMax];
+    __shared__ double red[kMP / kWave];
+    __shared__ int ok_sh;
+    int i = 0;
+    while (i + 1 < count && (int)blockIdx.x >= scans[i + 1].g0) ++i;
+    const ScanArgs sc = scans[i];
+    const int local = (int)blockIdx.x - sc.g0;
+    if (local < 0 || local >= sc.gn) return;
+    switch (sc.a.n) {
+        case 64: multi_scan<64>(sc, local, fault, lds, dl, red, &ok_sh); break;
+        case 128: multi_scan<128>(sc, local, fault, lds, dl, red, &ok_sh); break;
+        case 256: multi_scan<256>(sc, local, fault, lds, dl, red, &ok_sh); break;
     }
 }
 
-__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+// ---------------------------------------------------------------- sequential sweep
+// Strict (sequential) ePIE in one workgroup: the probe lives in LDS for the
+// whole sweep and is updated after every position, the N x N spectrum of
+// the current position stays in LDS between its row and column passes,
+// and the workgroup walks the order one position after another.  N x N2
+// threads: thread group l of N2 threads transforms row l in the row passes
+// and column l in the column pass, with the same passes, twiddles and
+// update expressions as the per-batch kernels, so a sweep gives the bytes
+// of the batch form with batches of one.  OL: the whole object is held in
+// LDS for the sweep (copied in at the start, out at the end) when it fits
+// beside the rest (kStrictObj<N> complex values), so a position's window
+// never waits for device memory; the next position's sqrt(I) is loaded
+// while the current one is transformed.
+template <int N> constexpr int kStrictNT = N * Fact<N>::N2;
+template <int N> constexpr int kStrictTP = N + 1;
+template <int N> constexpr int kStrictNW = kStrictNT<N> / kWave > 0 ? kStrictNT<N> / kWave : 1;
+// LDS of the kernel without the object, and what is left of the 160 KiB for it
+template <int N> constexpr int kStrictLdsBase =
+    (int)sizeof(cf) * (N * N + N * kStrictTP<N> + N * Lds<N>::LINE) + kStrictNW<N> * (2 * 4 + 8) + 64;
+template <int N> constexpr int kStrictObj = (160 * 1024 - kStrictLdsBase<N>) / (int)sizeof(cf);
+
+template <int N, bool OL>
+__global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count) {
+    using F = Fact<N>;
+    constexpr int N1 = F::N1, N2 = F::N2, NT = kStrictNT<N>, TP = kStrictTP<N>, NW = kStrictNW<N>;
+    __shared__ cf P[N * N];
+    __shared__ cf tile[N * TP];
+    __shared__ cf line[N * Lds<N>::LINE];
+    __shared__ float part[2][NW];
+    __shared__ double dsum[NW];
+    __shared__ cf objl[OL ? kStrictObj<N> : 1];
+    const int t = threadIdx.x % N2, l = threadIdx.x / N2;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    cf* z = line + l * Lds<N>::LINE;
+    cf wa[N1], wb[N1];
+    twiddles_a<N, -1>(wa, t, a.tw);
+    twiddles_binv<N, +1>(wb, t, a.tw);
+    const int64_t hw = a.h * a.w;
+    if constexpr (OL) {
+        for (int64_t e = threadIdx.x; e < hw; e += NT) objl[e] = a.obj[e];
+    }
+    cf* const obase = OL ? objl : a.obj;
+    // block maximum of per-thread values (uniform result); slot k of part
+    auto block_max = [&](float m, int k) {
+        m = wave_max(m);
+        if (lane == 0) part[k][wid] = m;
+        __syncthreads();
+        float r = part[k][0];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) r = fmaxf(r, part[k][i]);
+        return r;
+    };
+    // the probe row elements this thread owns in the row passes
+    float pm0 = 0.f;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        const int e = l * N + N2 * n1 + t;
+        const cf p = a.probe[e];
+        P[e] = p;
+        pm0 = fmaxf(pm0, norm2(p));
+    }
+    float pm = block_max(pm0, 0);
+    constexpr float inv = 1.0f / (float)(N * N);
+    // sqrt(I) of column l of a position, in the order the column pass holds it
+    auto load_amp = [&](int64_t j, float* amp) {
+        const float* ampb = a.sqrt_i + (size_t)j * N * N + l;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) amp[i] = ampb[(size_t)F::out(t, i) * N];
+    };
+    float amp[N1];
+    OrderEntry e = a.order[a.off];
+    load_amp(e.j, amp);
+    for (int k = 0; k < count; ++k) {
+        cf* orow = obase + (size_t)(e.row + l) * a.w + e.col;
+        cf o[N1], v[N1], p[N1];
+        float m = 0.f;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int col = N2 * n1 + t;
+            o[n1] = orow[col];
+            p[n1] = P[l * N + col];
+            m = fmaxf(m, norm2(o[n1]));
+            v[n1] = cmul(p[n1], o[n1]);
+        }
+        // the next position's sqrt(I), in flight during this one (issued
+        // after the object rows, whose wait therefore does not include it)
+        const OrderEntry en = a.order[a.off + (k + 1 < count ? k + 1 : k)];
+        float amp_next[N1];
+        load_amp(en.j, amp_next);
+        bool valid[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) valid[i] = a.mask == nullptr || a.mask[F::out(t, i) * N + l] != 0;
+        // row pass (forward): spectrum row l into the tile
+        passA_to_lds<N, -1>(v, z, t, wa);
+        __syncthreads();
+        passB_from_lds<N, -1, 1>(v, z, t);
+#pragma unroll
+        for (int i = 0; i < N1; ++i) tile[l * TP + F::out(t, i)] = v[i];
+        const float om = block_max(m, 1);   // its barrier also orders the tile writes
+        // column pass: column l, modulus replacement, inverse
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = tile[(N2 * n1 + t) * TP + l];
+        passA_to_lds<N, -1>(v, z, t, wa);
+        __syncthreads();
+        passB_from_lds<N, -1, 1>(v, z, t);
+        float err = 0.f;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+            const cf zz = v[i];
+            const float mag = sqrtf(norm2(zz));
+            const float d = mag - amp[i];
+            if (!valid[i]) continue;
+            err += d * d;
+            const float f = mag > 0.f ? amp[i] / mag : 0.f;
+            v[i] = f * zz;
+        }
+        __syncthreads();
+        passBinv_to_lds<N, +1, 1>(v, z, t, wb);
+        __syncthreads();
+        passAinv_from_lds<N, +1>(v, z, t);
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) tile[(N2 * n1 + t) * TP + l] = v[n1];
+        // error of this position (its own slot of the partials)
+        const double es = wave_sum((double)err);
+        if (lane == 0) dsum[wid] = es;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) tot += dsum[i];
+            a.err_part[a.off + k] = tot;
+        }
+        // inverse row pass: row l, then the object and probe steps
+#pragma unroll
+        for (int i = 0; i < N1; ++i) v[i] = tile[l * TP + F::out(t, i)];
+        passBinv_to_lds<N, +1, 1>(v, z, t, wb);
+        __syncthreads();
+        passAinv_from_lds<N, +1>(v, z, t);
+        const float ostep = a.alpha / pm;
+        const float pstep = 1.f / om;
+        float m2 = 0.f;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int col = N2 * n1 + t;
+            const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
+            orow[col] = axpy(ostep, cmulc(p[n1], delta), o[n1]);
+            // a batch of one: the increment sum starts from zero
+            const cf acc = cf{0.f, 0.f} + pstep * cmulc(o[n1], delta);
+            const cf pn = axpy(a.beta, acc, p[n1]);
+            P[l * N + col] = pn;
+            m2 = fmaxf(m2, norm2(pn));
+        }
+        // the next position reads rows of the object this one wrote (this
+        // workgroup's own stores, visible to it after the barrier)
+        pm = block_max(m2, 0);
+        e = en;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) amp[i] = amp_next[i];
+    }
+    if constexpr (OL) {
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < hw; q += NT) a.obj[q] = objl[q];
+    }
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        const int q = l * N + N2 * n1 + t;
+        a.probe[q] = P[q];
+    }
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
 
 // ---------------------------------------------------------------- ingest
 template <int N>
@@ -841,7 +1168,8 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
 constexpr int mix_tile_rb(int n) {
     return n == 64 ? MixTile<64>::RB : n == 128 ? MixTile<128>::RB : n == 256 ? MixTile<256>::RB : 0;
 }
-constexpr int mix_tile_r(int n) {
+constexpr int mix_tile_r(int n, int itile) {
+    if (itile) return n == 64 ? MixTile<64>::R2 : n == 128 ? MixTile<128>::R2 : n == 256 ? MixTile<256>::R2 : 0;
     return n == 64 ? MixTile<64>::R : n == 128 ? MixTile<128>::R : n == 256 ? MixTile<256>::R : 0;
 }
 template <int N>
@@ -1009,15 +1337,15 @@ int persistent_capacity_n() {
 }
 
 template <int N>
-hipError_t sweep_n(const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s) {
+hipError_t sweep_n(const ScanArgs& sc, int max_batch, int capacity, int* fault, hipStream_t s) {
     constexpr int TB = PTile<N>::B;
     const int need = std::max(max_batch * (N / TB), InvG<N, PTile<N>::R, PTile<N>::S>::GI);
-    const int grid = std::min(need, (int)c.nblocks);
-    SweepCtl cc = c;
-    cc.nblocks = (unsigned)grid;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, cc.bar);
-    BatchArgs aa = a;
-    void* args[] = {&aa, &cc};
+    const int grid = std::min(need, capacity);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, sc.bar, 1);
+    ScanArgs aa = sc;
+    aa.g0 = 0;
+    aa.gn = grid;
+    void* args[] = {&aa, &fault};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sweep<N>), dim3(grid), dim3(kSweepNT<N>),
                                       args, 0, s);
 }
@@ -1079,7 +1407,7 @@ hipError_t launch_batch_mixed(const BatchArgs* dev_tab, const BatchArgs* host_ta
         const int n = host_tab[i].n;
         if (!mixed_n(n) || host_tab[i].bsize < 0) return hipErrorInvalidValue;
         mr.start[i + 1] = mr.start[i] + n / mix_tile_rb(n) * host_tab[i].bsize;
-        mi.start[i + 1] = mi.start[i] + n / mix_tile_r(n);
+        mi.start[i + 1] = mi.start[i] + n / mix_tile_r(n, host_tab[i].itile);
     }
     if (mr.start[count] > 0) {
         hipLaunchKernelGGL(k_rows_fwd_mix, dim3(mr.start[count]), dim3(kMixRowNT), 0, s, mr);
@@ -1105,9 +1433,109 @@ int persistent_capacity(int n) {
     return 0;
 }
 
-hipError_t launch_sweep(int n, const BatchArgs& a, const SweepCtl& c, int max_batch, hipStream_t s) {
-    PTYC_DISPATCH(n, sweep_n<N>(a, c, max_batch, s));
+template <int N>
+hipError_t strict_n(const BatchArgs& a, int count, hipStream_t s) {
+    if constexpr (N <= kStrictMaxN) {
+        if (a.h * a.w <= kStrictObj<N>)
+            hipLaunchKernelGGL((k_strict<N, true>), dim3(1), dim3(kStrictNT<N>), 0, s, a, count);
+        else
+            hipLaunchKernelGGL((k_strict<N, false>), dim3(1), dim3(kStrictNT<N>), 0, s, a, count);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_strict(int n, const BatchArgs& a, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    PTYC_DISPATCH(n, strict_n<N>(a, count, s));
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep(int n, const ScanArgs& sc, int max_batch, int capacity, int* fault, hipStream_t s) {
+    PTYC_DISPATCH(n, sweep_n<N>(sc, max_batch, capacity, fault, s));
+    return hipErrorInvalidValue;
+}
+
+int multi_capacity() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_multi_persist), kMP, 0) !=
+        hipSuccess)
+        return 0;
+    return per * cus;
+}
+
+template <int N>
+int multi_need_n(int max_batch, int inv_tile) {
+    using t = MPTile<N>;
+    const int r = inv_tile ? t::R1 : t::R0;
+    return std::max(std::max(max_batch * (N / t::RB), max_batch * (N / t::CB)), N / r);
+}
+
+int multi_need(int n, int max_batch, int inv_tile) {
+    switch (n) {
+        case 64: return multi_need_n<64>(max_batch, inv_tile);
+        case 128: return multi_need_n<128>(max_batch, inv_tile);
+        case 256: return multi_need_n<256>(max_batch, inv_tile);
+    }
+    return 0;
+}
+
+int multi_col_blocks(int n) {
+    switch (n) {
+        case 64: return 64 / MPTile<64>::CB;
+        case 128: return 128 / MPTile<128>::CB;
+        case 256: return 256 / MPTile<256>::CB;
+    }
+    return 0;
+}
+
+hipError_t build_multi_graph(const ScanArgs* dev_scans, int count, int grid, unsigned* bars, int n_bars, int* fault,
+                             hipGraph_t* out) {
+    if (count <= 0 || count > kMultiMax || grid <= 0 || !out) return hipErrorInvalidValue;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t zero = nullptr, run = nullptr;
+    {
+        void* params[] = {&bars, &n_bars};
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void*>(&k_zero_u32);
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(64);
+        kp.kernelParams = params;
+        e = hipGraphAddKernelNode(&zero, g, nullptr, 0, &kp);
+    }
+    if (e == hipSuccess) {
+        void* params[] = {&dev_scans, &count, &fault};
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void*>(&k_multi_persist);
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(kMP);
+        kp.kernelParams = params;
+        e = hipGraphAddKernelNode(&run, g, &zero, 1, &kp);
+    }
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    *out = g;
+    return hipSuccess;
+}
+
+hipError_t launch_multi_persist(const ScanArgs* dev_scans, int count, int grid, unsigned* bars, int n_bars, int* fault,
+                                bool coop, hipStream_t s) {
+    if (count <= 0 || count > kMultiMax || grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bars, n_bars);
+    if (!coop) {
+        hipLaunchKernelGGL(k_multi_persist, dim3(grid), dim3(kMP), 0, s, dev_scans, count, fault);
+        return hipGetLastError();
+    }
+    void* args[] = {&dev_scans, &count, &fault};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_multi_persist), dim3(grid), dim3(kMP), args, 0,
+                                      s);
 }
 
 hipError_t build_sweep_graph(int n, int variant, const BatchArgs& a, int nb, int max_b, hipGraph_t* out) {

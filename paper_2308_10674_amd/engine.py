@@ -268,6 +268,15 @@ class Engine:
         _check(L.lib().ptyc_set_form(self._ctx, code), self._ctx)
 
     @property
+    def multi_variant(self) -> int:
+        """How a sweep_multi call led by this engine runs (see tune_multi)."""
+        return int(L.lib().ptyc_get_multi_variant(self._ctx))
+
+    @multi_variant.setter
+    def multi_variant(self, v):
+        _check(L.lib().ptyc_set_multi_variant(self._ctx, int(v)), self._ctx)
+
+    @property
     def num_positions(self) -> int:
         return int(L.lib().ptyc_num_positions(self._ctx))
 
@@ -304,6 +313,21 @@ def sweep_multi(engines, n_sweeps=1, errors=False):
         msgs = "; ".join(lib.ptyc_last_error(e._ctx).decode() for e in engines)
         raise L.PtycError(rc, msgs or "ptyc_sweep_multi failed")
     return err
+
+
+def tune_multi(engines, reps=2):
+    """Time every way ptyc_sweep_multi can run on one joint sweep of these
+    engines (state restored afterwards) and keep the fastest on the first
+    engine.  Returns (chosen variant, [best ms of each variant])."""
+    lib = L.lib()
+    arr = (C.c_void_p * len(engines))(*[e._ctx.value for e in engines])
+    v = C.c_int32()
+    ms = (C.c_double * L.PTYC_MULTI_VARIANTS)()
+    rc = lib.ptyc_tune_multi(arr, len(engines), int(reps), C.byref(v), ms)
+    if rc != L.PTYC_OK:
+        msgs = "; ".join(lib.ptyc_last_error(e._ctx).decode() for e in engines)
+        raise L.PtycError(rc, msgs or "ptyc_tune_multi failed")
+    return int(v.value), [float(ms[i]) for i in range(lib.ptyc_multi_variant_count())]
 
 
 def average(engines):

@@ -102,6 +102,61 @@ def test_multi_small_and_mixed_sizes_together():
         np.testing.assert_allclose(err_m[k], err_a, rtol=1e-13)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+def test_every_multi_variant_equals_individual_sweeps(variant):
+    """The persistent launches (one kernel, a group of workgroups and its
+    own barriers per scan; several inverse tiles and shares) and the
+    stepped launches all give each scan the bytes of its own sweeps."""
+    from paper_2308_10674_amd import sweep_multi
+    scans = _scans()
+    together = [engine_for(wl) for wl in scans]
+    together[0].multi_variant = variant
+    err_m = sweep_multi(together, 2, errors=True)
+    for k, (wl, e_tog) in enumerate(zip(scans, together)):
+        e_alone = engine_for(wl)
+        err_a = e_alone.sweep(2, errors=True)
+        np.testing.assert_array_equal(e_tog.get_object(), e_alone.get_object(), err_msg=f"scan {k}")
+        np.testing.assert_array_equal(e_tog.get_probe(), e_alone.get_probe(), err_msg=f"scan {k}")
+        np.testing.assert_allclose(err_m[k], err_a, rtol=1e-13)
+
+
+def test_multi_graph_form_replays():
+    """The persistent multi-scan launch captured as a graph, replayed by
+    three calls in a row (the second and third reuse the graph): the same
+    bytes as the cooperative launch."""
+    from paper_2308_10674_amd import sweep_multi
+    scans = _scans()
+    g = [engine_for(wl) for wl in scans]
+    b = [engine_for(wl) for wl in scans]
+    g[0].form = "graph"
+    for k in range(3):
+        eg = sweep_multi(g, 1, errors=True)
+        eb = sweep_multi(b, 1, errors=True)
+        np.testing.assert_allclose(eg, eb, rtol=0)
+    for e_g, e_b in zip(g, b):
+        np.testing.assert_array_equal(e_g.get_object(), e_b.get_object())
+        np.testing.assert_array_equal(e_g.get_probe(), e_b.get_probe())
+
+
+def test_tune_multi_keeps_state():
+    """The tuner times every variant and restores every scan's state and
+    sweep counter: a joint sweep after tuning equals one without it."""
+    from paper_2308_10674_amd import sweep_multi, tune_multi
+    scans = _scans()
+    t = [engine_for(wl) for wl in scans]
+    r = [engine_for(wl) for wl in scans]
+    sweep_multi(t, 1)
+    sweep_multi(r, 1)
+    v, ms = tune_multi(t, 1)
+    assert 0 <= v < len(ms) and all(m > 0 for m in ms)
+    assert all(e.sweeps_done == 1 for e in t)
+    sweep_multi(t, 1)
+    sweep_multi(r, 1)
+    for e_t, e_r in zip(t, r):
+        np.testing.assert_array_equal(e_t.get_object(), e_r.get_object())
+        np.testing.assert_array_equal(e_t.get_probe(), e_r.get_probe())
+
+
 def test_multi_rejects_bad_lists():
     from paper_2308_10674_amd import PtycError, sweep_multi
     scans = _scans()[:2]
