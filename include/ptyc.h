@@ -352,13 +352,32 @@ const char* ptyc_init_error(void);
  * for real functions of complex variables (dL/dRe + i dL/dIm):
  *   g_Psi = 2 (|Psi| - sqrt I) sgn(Psi), g_psi = F^H g_Psi,
  *   dL/dO[window j] += conj(P) g_psi,  dL/dP += conj(S_j O) g_psi.
- * Overlapping windows are accumulated in a fixed order (the minibatch is
- * split into batches of disjoint windows), so the result is deterministic.
- * Synchronises the stream.  Errors: PTYC_ERR_ARG for NULL buffers, an
- * index that is not loaded, only one gradient buffer, a non-finite scale. */
+ * The forward transforms of the whole minibatch run at once; overlapping
+ * windows are accumulated into dL/dO in a fixed order (the minibatch is
+ * split into batches of disjoint windows, taken one after another), so
+ * the result is deterministic.  Work buffers grow to the minibatch size
+ * (N^2 complex64 per position).  Synchronises the stream.  Errors:
+ * PTYC_ERR_ARG for NULL buffers, an index that is not loaded, only one
+ * gradient buffer, a non-finite scale. */
 int ptyc_amp_loss(ptyc_ctx* ctx, const void* obj, const void* probe, const int64_t* idx,
                   int64_t count, float grad_scale, void* grad_obj, void* grad_probe,
                   double* loss_out);
+
+/* ptyc_amp_loss without waiting for the result: the loss is written to the
+ * device double loss_dev and the gradients (grad_scale 1) to grad_obj and
+ * grad_probe (both or neither) when the enqueued work runs; nothing on the
+ * host waits for the stream (only for the previous upload of an index
+ * list, if it is still in flight).  For an optimiser loop: the autograd
+ * wrapper computes loss and gradients in its forward and scales the saved
+ * gradients by the upstream gradient (ptyc_scale_c64) in its backward.
+ * Errors as for ptyc_amp_loss. */
+int ptyc_amp_loss_async(ptyc_ctx* ctx, const void* obj, const void* probe, const int64_t* idx,
+                        int64_t count, void* grad_obj, void* grad_probe, double* loss_dev);
+
+/* Multiply `count` complex64 values at the device pointer data in place by
+ * the device double *scale_dev (rounded to float), on the context's
+ * stream.  Errors: PTYC_ERR_ARG for NULL buffers or a negative count. */
+int ptyc_scale_c64(ptyc_ctx* ctx, void* data, int64_t count, const double* scale_dev);
 
 /* ---- host-only helpers (no device needed) ---- */
 

@@ -81,6 +81,8 @@ SIGNATURES = {
     "ptyc_set_object": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_set_probe": (C.c_int, [_P, _P, C.c_int]),
     "ptyc_amp_loss": (C.c_int, [_P, _P, _P, _I64P, C.c_int64, C.c_float, _P, _P, _DP]),
+    "ptyc_amp_loss_async": (C.c_int, [_P, _P, _P, _I64P, C.c_int64, _P, _P, _P]),
+    "ptyc_scale_c64": (C.c_int, [_P, _P, C.c_int64, _P]),
     "ptyc_set_form": (C.c_int, [_P, C.c_int]),
     "ptyc_profile": (C.c_int, [_P, C.c_int]),
     "ptyc_profile_read": (C.c_int, [_P, C.c_int, _DP, _I64P, _I64P]),

@@ -1,7 +1,9 @@
 """Differentiable amplitude loss: a torch.autograd.Function whose forward
-and backward both run in libptyc's kernels (forward: row and column FFTs of
-P * S_j O and the loss; backward: the hand-written adjoint, accumulating
-dL/dO over overlapping windows and dL/dP in a fixed order)."""
+and backward both run in libptyc's kernels.  The forward runs the row and
+column FFTs of P * S_j O, the loss and the hand-written adjoint
+(accumulating dL/dO over overlapping windows and dL/dP in a fixed order) in
+one enqueued pass, without waiting for the GPU; the backward scales the
+saved gradients by the upstream gradient."""
 from __future__ import annotations
 
 import torch
@@ -17,17 +19,21 @@ class AmplitudeLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, obj, probe, engine, idx):
-        loss = engine.amp_loss(obj, probe, idx)
+        # loss and, when an input needs it, both gradients in one pass of
+        # the kernels; nothing here waits for the GPU
+        grad = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+        loss, g_obj, g_probe = engine.amp_loss_async(obj, probe, idx, grad=grad)
         ctx.engine = engine
-        ctx.idx = idx
-        ctx.save_for_backward(obj, probe)
-        return torch.tensor(loss, dtype=torch.float64, device=obj.device)
+        ctx.grads = (g_obj, g_probe)
+        return loss
 
     @staticmethod
     def backward(ctx, grad_out):
-        obj, probe = ctx.saved_tensors
-        scale = float(grad_out)
-        _, g_obj, g_probe = ctx.engine.amp_loss(obj, probe, ctx.idx, grad=True, scale=scale)
+        g_obj, g_probe = ctx.grads
+        ctx.grads = None
+        # the upstream gradient scales the saved gradients (library kernel)
+        ctx.engine.scale_(g_obj, grad_out)
+        ctx.engine.scale_(g_probe, grad_out)
         return g_obj, g_probe, None, None
 
 

@@ -1511,11 +1511,19 @@ int ptyc_average(ptyc_ctx* const* ctxs, int32_t n_ctx) {
     return PTYC_OK;
 }
 
-int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,
-                  float grad_scale, void* grad_obj, void* grad_probe, double* loss_out) {
-    int rc = usable(c);
-    if (rc) return rc;
-    if (!obj || !probe || !loss_out) return fail(c, PTYC_ERR_ARG, "obj, probe and loss_out must not be NULL");
+}  // extern "C"
+
+namespace {
+
+// The amplitude loss (and its gradient) of a minibatch, enqueued on the
+// context's stream: the forward stages over the whole minibatch in one
+// launch pair (they write nothing but the exchange and the loss partials),
+// then, for the gradient, the adjoint's row stage once per batch of
+// disjoint windows (overlapping windows accumulate into dL/dO one batch
+// after another, a fixed order); the loss sum lands in loss_dev.
+int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,
+                     float grad_scale, void* grad_obj, void* grad_probe, double* loss_dev) {
+    if (!obj || !probe) return fail(c, PTYC_ERR_ARG, "obj and probe must not be NULL");
     if ((grad_obj == nullptr) != (grad_probe == nullptr))
         return fail(c, PTYC_ERR_ARG, "grad_obj and grad_probe must both be given or both be NULL");
     if (count < 0 || (count > 0 && !idx)) return fail(c, PTYC_ERR_ARG, "bad index list");
@@ -1523,6 +1531,7 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
     for (int64_t i = 0; i < count; ++i)
         if (idx[i] < 0 || idx[i] >= c->n_loaded)
             return fail(c, PTYC_ERR_ARG, "index " + std::to_string(idx[i]) + " is not a loaded position");
+    int rc;
     const bool grad = grad_obj != nullptr;
     const int n = c->cfg.n;
     const size_t nn = (size_t)n * n;
@@ -1530,12 +1539,8 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
         HIPCHK(c, launch_fill_zero(grad_obj, (int64_t)c->cfg.h * c->cfg.w, c->stream));
         HIPCHK(c, launch_fill_zero(grad_probe, (int64_t)nn, c->stream));
     }
-    if (count == 0) {
-        *loss_out = 0.0;
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        return PTYC_OK;
-    }
-    // batches of disjoint windows inside the minibatch (greedy, in list order)
+    // batches of disjoint windows inside the minibatch (greedy, in list
+    // order); the forward stages run over the concatenation at once
     std::vector<int32_t> mp((size_t)(2 * count));
     for (int64_t i = 0; i < count; ++i) {
         mp[(size_t)(2 * i)] = c->h_pos[(size_t)(2 * idx[i])];
@@ -1544,43 +1549,94 @@ int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t
     Colouring col(n, max_batch_of(c));
     col.extend(mp.data(), 0, count);
     std::vector<int64_t> order, off{0};
+    order.reserve((size_t)count);
     for (const auto& m : col.members()) {
         for (int64_t k : m) order.push_back(idx[k]);
         off.push_back((int64_t)order.size());
     }
-    int64_t max_b = 1;
-    for (size_t b = 0; b + 1 < off.size(); ++b) max_b = std::max(max_b, off[b + 1] - off[b]);
-    if (max_b > c->slots) {
-        if ((rc = ensure(c, c->scratch, (size_t)max_b * nn * sizeof(cf))) != PTYC_OK) return rc;
-        if ((rc = ensure(c, c->winmax, (size_t)max_b * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
-        c->slots = max_b;
+    const int64_t slots = std::max<int64_t>(count, 1);
+    if (slots > c->slots) {
+        if ((rc = ensure(c, c->scratch, (size_t)slots * nn * sizeof(cf))) != PTYC_OK) return rc;
+        if ((rc = ensure(c, c->winmax, (size_t)slots * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
+        c->slots = slots;
     }
-    std::vector<OrderEntry> ents((size_t)count);
-    to_entries(c, order.data(), count, ents.data());
     const size_t obytes = (size_t)count * sizeof(OrderEntry);
+    // the pinned upload buffer may still feed an earlier copy
     if (c->upload_pending) {
         HIPCHK(c, hipEventSynchronize(c->upload_done));
         c->upload_pending = false;
     }
-    if ((rc = ensure(c, c->order, obytes)) != PTYC_OK) return rc;
-    if ((rc = ensure(c, c->err_part, (size_t)count * c->sb.col_blocks * sizeof(double))) != PTYC_OK) return rc;
-    if ((rc = ensure(c, c->err_dev, sizeof(double))) != PTYC_OK) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->order.p, ents.data(), obytes, hipMemcpyHostToDevice, c->stream));
+    if ((rc = ensure(c, c->order, std::max<size_t>(obytes, sizeof(OrderEntry)))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->err_part, (size_t)slots * c->sb.col_blocks * sizeof(double))) != PTYC_OK) return rc;
+    if (c->pinned_bytes < obytes) {
+        if (c->pinned_order) (void)hipHostFree(c->pinned_order);
+        c->pinned_order = nullptr;
+        c->pinned_bytes = 0;
+        hipError_t e = hipHostMalloc((void**)&c->pinned_order, obytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, PTYC_ERR_OOM, "pinned host allocation failed");
+        }
+        c->pinned_bytes = obytes;
+    }
+    if (count > 0) {
+        to_entries(c, order.data(), count, (OrderEntry*)c->pinned_order);
+        HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, obytes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
+        c->upload_pending = true;
+    }
     BatchArgs a = base_args(c);
     a.obj = (cf*)obj;
     a.probe = (cf*)probe;
     a.gobj = (cf*)grad_obj;
     a.gprobe = (cf*)grad_probe;
     a.gscale = grad_scale;
-    for (size_t b = 0; b + 1 < off.size(); ++b) {
-        a.off = off[b];
-        a.bsize = (int)(off[b + 1] - off[b]);
-        HIPCHK(c, launch_loss(n, a, grad, c->stream));
+    a.off = 0;
+    a.bsize = (int)count;
+    HIPCHK(c, launch_loss_fwd(n, a, grad, c->stream));
+    if (grad) {
+        for (size_t b = 0; b + 1 < off.size(); ++b) {
+            a.off = off[b];
+            a.bsize = (int)(off[b + 1] - off[b]);
+            a.scratch = (cf*)c->scratch.p + (size_t)off[b] * nn;
+            HIPCHK(c, launch_grad_rows(n, a, c->stream));
+        }
     }
-    HIPCHK(c, launch_sum_reduce((const double*)c->err_part.p, count * c->sb.col_blocks, (double*)c->err_dev.p,
-                                c->stream));
+    HIPCHK(c, launch_sum_reduce((const double*)c->err_part.p, count * c->sb.col_blocks, loss_dev, c->stream));
+    return PTYC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ptyc_amp_loss(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,
+                  float grad_scale, void* grad_obj, void* grad_probe, double* loss_out) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!loss_out) return fail(c, PTYC_ERR_ARG, "loss_out must not be NULL");
+    if ((rc = ensure(c, c->err_dev, sizeof(double))) != PTYC_OK) return rc;
+    if ((rc = amp_loss_enqueue(c, obj, probe, idx, count, grad_scale, grad_obj, grad_probe,
+                               (double*)c->err_dev.p)) != PTYC_OK)
+        return rc;
     HIPCHK(c, hipMemcpyAsync(loss_out, c->err_dev.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTYC_OK;
+}
+
+int ptyc_amp_loss_async(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,
+                        void* grad_obj, void* grad_probe, double* loss_dev) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!loss_dev) return fail(c, PTYC_ERR_ARG, "loss_dev must not be NULL");
+    return amp_loss_enqueue(c, obj, probe, idx, count, 1.0f, grad_obj, grad_probe, loss_dev);
+}
+
+int ptyc_scale_c64(ptyc_ctx* c, void* data, int64_t count, const double* scale_dev) {
+    int rc = usable(c);
+    if (rc) return rc;
+    if (count < 0 || (count > 0 && (!data || !scale_dev))) return fail(c, PTYC_ERR_ARG, "bad buffer or count");
+    HIPCHK(c, launch_scale(data, count, scale_dev, c->stream));
     return PTYC_OK;
 }
 

@@ -146,9 +146,17 @@ hipError_t build_multi_graph(const ScanArgs* dev_scans, int count, int grid, uns
 // node, empty or not, writes the other half), so after the graph the
 // current maxima are in a.pmax_in when nb is even, else in a.pmax_out.
 hipError_t build_sweep_graph(int n, int variant, const BatchArgs& a, int nb, int max_b, hipGraph_t* out);
-// amplitude loss over one batch of disjoint windows; grad: also accumulate
-// dL/dO into gobj and dL/dP into gprobe
-hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s);
+// Amplitude loss, forward stages over a.bsize positions a.order[a.off ..]
+// (windows may overlap), slot k's spectrum at a.scratch + k N^2; loss
+// partials into a.err_part; grad: the column stage leaves dL/dpsi's row
+// transforms in the exchange for launch_grad_rows.
+hipError_t launch_loss_fwd(int n, const BatchArgs& a, bool grad, hipStream_t s);
+// the adjoint's row stage for one batch of disjoint windows (a.scratch
+// pointing at the batch's first slot): accumulates dL/dO into gobj and
+// dL/dP into gprobe
+hipError_t launch_grad_rows(int n, const BatchArgs& a, hipStream_t s);
+// multiply count complex values in place by the device scalar *scale
+hipError_t launch_scale(void* p, int64_t count_c64, const double* scale, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s);
 // replace each of the k arrays (count_c64 complex values each) by their mean
 hipError_t launch_mean(void* const* ptrs, int k, int64_t count_c64, hipStream_t s);

@@ -1310,19 +1310,34 @@ hipError_t probe_n(const BatchArgs& a, int form, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The forward stages of the amplitude loss over a.bsize positions at once
+// (windows may overlap: nothing is written to the object): exit wave and
+// row FFTs, then the column stage computing the loss partials and, with
+// grad, g_Psi transformed back to the rows of dL/dpsi in the exchange.
 template <int N>
-hipError_t loss_n(const BatchArgs& a, bool grad, hipStream_t s) {
+hipError_t loss_fwd_n(const BatchArgs& a, bool grad, hipStream_t s) {
     using rg = RowG<N, Tile<N>::RB>;
     using cg = ColG<N, Tile<N>::CB>;
     if (a.bsize <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rows_fwd<N>, dim3(rg::G * a.bsize), dim3(rg::NT), 0, s, a);
-    if (grad) {
+    if (grad)
         hipLaunchKernelGGL((k_cols_mode<N, kModeGrad>), dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
-        hipLaunchKernelGGL(k_rows_grad<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
-    } else {
+    else
         hipLaunchKernelGGL((k_cols_mode<N, kModeLoss>), dim3(cg::GC * a.bsize), dim3(cg::NT), 0, s, a);
-    }
     return hipGetLastError();
+}
+
+// the adjoint's row stage for one batch of disjoint windows
+template <int N>
+hipError_t grad_rows_n(const BatchArgs& a, hipStream_t s) {
+    if (a.bsize <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows_grad<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_scale_c64(cf* p, int64_t n, const double* scale) {
+    const float f = (float)*scale;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = f * p[i];
 }
 
 template <int N>
@@ -1544,9 +1559,21 @@ hipError_t build_sweep_graph(int n, int variant, const BatchArgs& a, int nb, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_loss(int n, const BatchArgs& a, bool grad, hipStream_t s) {
-    PTYC_DISPATCH(n, loss_n<N>(a, grad, s));
+hipError_t launch_loss_fwd(int n, const BatchArgs& a, bool grad, hipStream_t s) {
+    PTYC_DISPATCH(n, loss_fwd_n<N>(a, grad, s));
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_grad_rows(int n, const BatchArgs& a, hipStream_t s) {
+    PTYC_DISPATCH(n, grad_rows_n<N>(a, s));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scale(void* p, int64_t count_c64, const double* scale, hipStream_t s) {
+    if (count_c64 <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count_c64 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_scale_c64, dim3((unsigned)blocks), dim3(256), 0, s, (cf*)p, count_c64, scale);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s) {

@@ -216,6 +216,36 @@ class Engine:
                                      C.byref(loss)), self._ctx)
         return (loss.value, go, gp) if grad else loss.value
 
+    def amp_loss_async(self, obj, probe, idx, grad=True):
+        """Loss (a float64 CUDA scalar tensor) and, with ``grad``, dL/dO and
+        dL/dP as new device tensors, all filled in when the enqueued work
+        runs on the stream (nothing waits for it here)."""
+        o = obj.detach()
+        p = probe.detach()
+        if not (o.is_cuda and p.is_cuda) or o.dtype != torch.complex64 or p.dtype != torch.complex64:
+            raise ValueError("obj and probe must be complex64 CUDA tensors")
+        o = o.contiguous()
+        p = p.contiguous()
+        ia, ip = _i64(np.asarray(idx, dtype=np.int64).ravel())
+        loss = torch.empty((), dtype=torch.float64, device=o.device)
+        go = torch.empty_like(o) if grad else None
+        gp = torch.empty_like(p) if grad else None
+        _check(L.lib().ptyc_amp_loss_async(self._ctx, o.data_ptr(), p.data_ptr(), ip, len(ia),
+                                           go.data_ptr() if grad else None, gp.data_ptr() if grad else None,
+                                           loss.data_ptr()), self._ctx)
+        # the inputs and outputs must outlive the enqueued work: torch's
+        # caching allocator reuses freed blocks only in stream order
+        return loss, go, gp
+
+    def scale_(self, data, scale_dev):
+        """data (complex64 CUDA tensor) *= scale_dev (float64 CUDA scalar),
+        in place, on the library's stream."""
+        if not data.is_contiguous() or data.dtype != torch.complex64:
+            raise ValueError("data must be a contiguous complex64 tensor")
+        s = scale_dev.detach().to(torch.float64).contiguous()
+        _check(L.lib().ptyc_scale_c64(self._ctx, data.data_ptr(), data.numel(), s.data_ptr()), self._ctx)
+        return data
+
     # ------------------------------------------------------------ profiling
     def profile(self, enable=True):
         """Start (reset) or stop per-kernel event timing."""

@@ -26,7 +26,7 @@ def _lib():
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ptyc_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ptyc_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():

@@ -183,6 +183,23 @@ def test_gradient_equals_scaled_epie_step(problem, torch_cuda):
     assert r <= 1e-4, r   # the step is a small difference of FP32 numbers near 1
 
 
+def test_async_loss_equals_synchronous(problem, torch_cuda):
+    """ptyc_amp_loss_async (device loss, no wait) gives the bytes of
+    ptyc_amp_loss, and the library's in-place scale is a plain float
+    multiply."""
+    torch = torch_cuda
+    pr = problem
+    L, go, gp = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True)
+    Ld, god, gpd = pr["eng"].amp_loss_async(pr["to"], pr["tp"], pr["idx"], grad=True)
+    Lo = pr["eng"].amp_loss_async(pr["to"], pr["tp"], pr["idx"], grad=False)[0]
+    assert float(Ld) == L and float(Lo) == L
+    assert bool((god == go).all()) and bool((gpd == gp).all())
+    s = torch.tensor(0.37, dtype=torch.float64, device="cuda")
+    ref = go.cpu().numpy() * np.float32(0.37)
+    pr["eng"].scale_(god, s)
+    np.testing.assert_array_equal(god.cpu().numpy(), ref)
+
+
 def test_autograd_function(problem, torch_cuda):
     torch = torch_cuda
     from paper_2308_10674_amd import amplitude_loss
@@ -191,8 +208,14 @@ def test_autograd_function(problem, torch_cuda):
     P = pr["tp"].clone().requires_grad_(True)
     loss = amplitude_loss(pr["eng"], O, P, pr["idx"])
     (3.0 * loss).backward()
-    _, go, gp = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True, scale=3.0)
-    assert bool((O.grad == go).all()) and bool((P.grad == gp).all())
+    L1, go, gp = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True)
+    assert float(loss.detach()) == L1
+    # the saved gradients times the upstream gradient (3), one float multiply
+    np.testing.assert_array_equal(O.grad.cpu().numpy(), go.cpu().numpy() * np.float32(3.0))
+    np.testing.assert_array_equal(P.grad.cpu().numpy(), gp.cpu().numpy() * np.float32(3.0))
+    # the scaled-inside gradient of ptyc_amp_loss agrees to rounding
+    _, go3, gp3 = pr["eng"].amp_loss(pr["to"], pr["tp"], pr["idx"], grad=True, scale=3.0)
+    np.testing.assert_allclose(O.grad.cpu().numpy(), go3.cpu().numpy(), rtol=1e-5, atol=1e-6 * float(go3.abs().max()))
 
 
 def test_directional_derivative(problem, torch_cuda):
