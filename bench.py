@@ -105,13 +105,19 @@ def run_gpu(cfg_id, steps, warmup, form, positions=None, tile=None):
     sizes = np.diff(off)
     eng.sweep(warmup)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    eng.sweep(steps)
-    stop.record()
+    # exactly `steps` sweeps between the first and the last event; the
+    # events between them split the run into (up to) five segments whose
+    # per-sweep times give the median reported beside the total
+    segs = [steps // 5 + (1 if k < steps % 5 else 0) for k in range(5)]
+    segs = [k for k in segs if k > 0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(segs) + 1)]
+    ev[0].record()
+    for k, n_s in enumerate(segs):
+        eng.sweep(n_s)
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    ms = ev[0].elapsed_time(ev[-1])
+    seg_ms = [ev[k].elapsed_time(ev[k + 1]) / segs[k] for k in range(len(segs))]
     err = eng.sweep(1, errors=True)[0]
     updates = wl.count * steps
     rate = updates / (ms / 1e3)
@@ -122,7 +128,7 @@ def run_gpu(cfg_id, steps, warmup, form, positions=None, tile=None):
     eng.sweep(steps)
     kern = eng.profile_read()
     eng.profile(False)
-    return dict(wl=wl, ms=ms, rate=rate, achieved_gbs=achieved, batches=int(len(sizes)),
+    return dict(wl=wl, ms=ms, seg_ms=seg_ms, rate=rate, achieved_gbs=achieved, batches=int(len(sizes)),
                 mean_batch=float(sizes.mean()), max_batch=int(sizes.max()), gen_s=gen_s,
                 ingest_s=ingest_s, err=float(err), kernels=kern, tile=tile,
                 tile_ms=[round(m, 4) for m in tile_ms])
@@ -130,7 +136,9 @@ def run_gpu(cfg_id, steps, warmup, form, positions=None, tile=None):
 
 def run_forms(wl, steps, strict_steps=1):
     """Updates/s of the other launch forms on the same workload: the sweep
-    graph, the persistent kernel, and strict ePIE (every position its own
+    graph, the persistent kernel (one cooperative launch per sweep with
+    software barriers between the stages; slower here than three launches
+    per batch, kept for comparison), and strict ePIE (every position its own
     batch: one group of three launches per position)."""
     import torch
 
@@ -156,6 +164,85 @@ def run_forms(wl, steps, strict_steps=1):
         eng.close()
     out["unit"] = "position updates/s"
     return out
+
+
+def run_config0(steps=20):
+    """Sequential ePIE on the 32 px workload (10 x 10 raster, 128 x 128
+    object), one sweep per step in the paper's order semantics: one group
+    of three launches per position against the one-workgroup sequential
+    kernel (the persistent form in strict mode)."""
+    import torch
+
+    import sim
+    from paper_2308_10674_amd import Engine
+
+    wl = sim.make_config(0)
+    out = {"workload": "32x32 patterns, 10x10 raster (100 positions), 128x128 object, sequential (strict) ePIE",
+           "unit": "position updates/s"}
+    for name, form, k in (("per_position_launches", "batch", max(2, steps // 4)), ("sequential_kernel", "persistent", steps)):
+        eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="strict", seed=wl.seed, form=form)
+        eng.add_positions(wl.positions, wl.intensities)
+        eng.sweep(2)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        eng.sweep(k)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        out[name] = {"value": round(wl.count * k / (ms / 1e3), 1), "ms_per_step": round(ms / k, 4), "steps": k}
+        eng.close()
+    return out
+
+
+def run_gradient(epochs=10, minibatch=512, lr=1e-2):
+    """Gradient reconstruction throughput on the 128 px workload (3600
+    positions, 1024 x 1024 object): Adam over shuffled minibatches of 512
+    with the amplitude loss and its hand-written adjoint (AmplitudeLoss),
+    timed over `epochs` epochs after one warm-up epoch.  Rate: position
+    gradients per second (one position's loss term and its contribution to
+    dL/dO and dL/dP).  Path roofline: 28 N^2 algorithmic bytes per position
+    gradient (read sqrt(I) 4 N^2, read the window 8 N^2, read and write the
+    window of dL/dO 16 N^2); Adam's own update of O and P is not counted."""
+    import torch
+
+    import sim
+    from paper_2308_10674_amd import Engine, amplitude_loss
+
+    wl = sim.make_config(3)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(torch.from_numpy(wl.positions).cuda(), torch.from_numpy(wl.intensities).cuda())
+    O = torch.from_numpy(wl.object0.astype(np.complex64)).cuda().requires_grad_(True)
+    P = torch.from_numpy(wl.probe0.astype(np.complex64)).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([O, P], lr=lr)
+    rng = np.random.default_rng([wl.seed, 9])
+
+    def epoch():
+        perm = rng.permutation(wl.count)
+        for b in range(0, wl.count, minibatch):
+            opt.zero_grad(set_to_none=True)
+            amplitude_loss(eng, O, P, perm[b:b + minibatch]).backward()
+            opt.step()
+
+    epoch()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(epochs):
+        epoch()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    rate = wl.count * epochs / (ms / 1e3)
+    gbs = 28 * wl.n * wl.n * rate / 1e9
+    err = eng.amp_loss(O.detach(), P.detach(), np.arange(wl.count)) / float(wl.intensities.sum(dtype=np.float64))
+    eng.close()
+    return {"workload": "128x128 patterns, 60x60 raster (3600 positions), 1024x1024 object; Adam lr 1e-2, "
+                        f"minibatches of {minibatch}, {epochs} timed epochs",
+            "value": round(rate, 1), "unit": "position gradients/s", "ms_per_epoch": round(ms / epochs, 3),
+            "path": {"achieved": round(gbs, 2), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                     "bytes_per_position_gradient": 28 * wl.n * wl.n},
+            "error_after": round(float(err), 6)}
 
 
 def run_live(wl, tile=None):
@@ -211,6 +298,8 @@ def roofline_of(r):
         "traffic_GBps": None if tr is None else round(tr["bytes_per_launch"] / avg_s / 1e9, 2),
         "algorithmic_bytes_per_launch": round(per_launch_bytes),
         "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
+        "timing": "HIP events bound to each launch of the kernel (hipExtLaunchKernel) on its stream, "
+                  "summed over one run of the timed number of sweeps",
         "kernel_times_ms": {k: round(v[0], 3) for k, v in r["kernels"].items()},
     }
 
@@ -245,7 +334,7 @@ def run_multi(steps, warmup, n_scans=16):
     import torch
 
     import sim
-    from paper_2308_10674_amd import Engine, sweep_multi
+    from paper_2308_10674_amd import Engine, sweep_multi, tune_multi
 
     t0 = time.time()
     scans = sim.make_multiscan(n_scans)
@@ -257,30 +346,39 @@ def run_multi(steps, warmup, n_scans=16):
         engs.append(e)
         wl.intensities = None
     total = sum(wl.count for wl in scans)
+    bytes_per_sweep = sum(20 * wl.n * wl.n * wl.count for wl in scans)
     sweep_multi(engs, warmup)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record()
-    for e in engs:
-        e.sweep(steps)
-    ev[1].record()
-    ev[2].record()
-    sweep_multi(engs, steps)
-    ev[3].record()
-    torch.cuda.synchronize()
-    ms_seq = ev[0].elapsed_time(ev[1])
-    ms_multi = ev[2].elapsed_time(ev[3])
-    bytes_per_sweep = sum(20 * wl.n * wl.n * wl.count for wl in scans)
-    return {
+
+    def timed(fn):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        gbs = bytes_per_sweep * steps / (ms / 1e3) / 1e9
+        return {"value": round(total * steps / (ms / 1e3), 1), "ms_per_step": round(ms / steps, 3),
+                "achieved": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 5)}
+
+    out = {
         "workload": f"{n_scans} independent scans, pattern sizes {sorted(set(int(wl.n) for wl in scans))}, "
                     f"{total} positions in total ({min(wl.count for wl in scans)}-{max(wl.count for wl in scans)} per scan)",
-        "steps": steps, "generation_s": round(gen_s, 1),
-        "sequential": {"value": round(total * steps / (ms_seq / 1e3), 1), "ms_per_step": round(ms_seq / steps, 3)},
-        "together": {"value": round(total * steps / (ms_multi / 1e3), 1), "ms_per_step": round(ms_multi / steps, 3),
-                     "achieved": round(bytes_per_sweep * steps / (ms_multi / 1e3) / 1e9, 2),
-                     "frac": round(bytes_per_sweep * steps / (ms_multi / 1e3) / 1e9 / HBM_PEAK_GBS, 5)},
-        "unit": "position updates/s",
+        "steps": steps, "generation_s": round(gen_s, 1), "unit": "position updates/s",
+        "sequential": timed(lambda: [e.sweep(steps) for e in engs]),
     }
+    names = {2: "persistent_per_scan_barriers", 4: "stepped", 6: "stepped_small_batch_tile"}
+    for v, name in names.items():
+        engs[0].multi_variant = v
+        out[name] = timed(lambda: sweep_multi(engs, steps))
+    best, ms = tune_multi(engs, 1)
+    out["tuned"] = {"variant": best, "variant_names": {str(k): n for k, n in names.items()},
+                    "ms_per_variant_one_sweep": [round(m, 3) for m in ms]}
+    out["together"] = timed(lambda: sweep_multi(engs, steps))
+    out["together"]["variant"] = best
+    for e in engs:
+        e.close()
+    return out
 
 
 def run_adam_vs_epie(epochs, minibatch, lr, max_sweeps):
@@ -391,6 +489,76 @@ def cpu_baseline(cfg_id, budget_s, wl256=None):
                 other_configs=cpu_other_configs(max(1.0, budget_s / 5), wl256))
 
 
+def cpu_worker(data_dir, k, n_workers, budget_s):
+    """One all-cores baseline worker (a child process): the oracle on the
+    coloured batches of the 128 px workload, in schedule order from its
+    own starting batch, for budget_s seconds; prints its update count."""
+    import oracle
+
+    pos = np.load(os.path.join(data_dir, "positions.npy"))
+    inten = np.load(os.path.join(data_dir, "intensities.npy"), mmap_mode="r")
+    O = np.load(os.path.join(data_dir, "object0.npy"))
+    P = np.load(os.path.join(data_dir, "probe0.npy"))
+    base = np.load(os.path.join(data_dir, "order.npy"))
+    off = np.load(os.path.join(data_dir, "offsets.npy"))
+    nc = len(off) - 1
+    done, b = 0, (k * nc) // n_workers
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        idx = base[off[b % nc]:off[b % nc + 1]]
+        O, P, _, _ = oracle.sweep_coloured(O, P, pos[idx], np.asarray(inten[idx]), np.arange(len(idx)),
+                                           [0, len(idx)], check=False)
+        done += len(idx)
+        b += 1
+    print(json.dumps({"updates": done, "seconds": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_baseline_all_cores(budget_s):
+    """The same FP64 oracle on every host core at once: one single-threaded
+    oracle process per core (started as child processes), each running the
+    128 px workload's coloured batches from its own starting batch and the
+    same starting state; the aggregate rate is the sum of their updates over
+    the longest run.  A throughput of the unmodified oracle, not one
+    coherent reconstruction (a sweep's batches depend on each other)."""
+    import subprocess
+    import tempfile
+
+    import sim
+    from paper_2308_10674_amd import colour
+
+    try:
+        n_workers = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n_workers = os.cpu_count() or 1
+    wl = sim.make_config(1)
+    col, nc = colour(wl.positions, wl.n)
+    with tempfile.TemporaryDirectory(dir="/tmp") as d:
+        np.save(os.path.join(d, "positions.npy"), wl.positions)
+        np.save(os.path.join(d, "intensities.npy"), wl.intensities)
+        np.save(os.path.join(d, "object0.npy"), wl.object0)
+        np.save(os.path.join(d, "probe0.npy"), wl.probe0)
+        np.save(os.path.join(d, "order.npy"), np.argsort(col, kind="stable"))
+        np.save(os.path.join(d, "offsets.npy"), np.concatenate([[0], np.cumsum(np.bincount(col))]))
+        del wl
+        env = dict(os.environ)
+        for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[v] = "1"
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", d, str(k),
+                                   str(n_workers), str(budget_s)], stdout=subprocess.PIPE, env=env, text=True)
+                 for k in range(n_workers)]
+        res = []
+        for p in procs:
+            out, _ = p.communicate(timeout=budget_s * 10 + 120)
+            if p.returncode != 0:
+                raise RuntimeError(f"CPU baseline worker failed with status {p.returncode}")
+            res.append(json.loads(out.strip().splitlines()[-1]))
+    upd = sum(r["updates"] for r in res)
+    sec = max(r["seconds"] for r in res)
+    return {"value": upd / sec, "unit": "position updates/s", "cores": n_workers, "kind": "oracle",
+            "sample": f"{n_workers} single-threaded FP64 numpy oracle processes on the 128 px workload's coloured "
+                      f"batches, {upd} position updates in {sec:.1f} s"}
+
+
 def cpu_other_configs(budget_s, wl256=None):
     """The same oracle on the other two pattern sizes, briefly: the 32 px
     raster swept strictly (sequential ePIE, whole sweeps) and, when the
@@ -454,10 +622,18 @@ def main():
                     help="only compare gradient reconstruction (Adam) with ePIE at equal Fourier error")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-all-seconds", type=float, default=10.0,
+                    help="budget of the all-cores oracle baseline (0 skips it)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 32 px sequential and the gradient workloads")
+    ap.add_argument("--cpu-worker", nargs=4, metavar=("DIR", "K", "WORKERS", "SECONDS"), help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy kernel (x -> -x), three times, to scale "
                          "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker[0], int(args.cpu_worker[1]), int(args.cpu_worker[2]), float(args.cpu_worker[3]))
+        return
     if args.calibrate_copy:
         import torch
         x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
@@ -489,6 +665,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms"] / args.steps, 4),
+        "median_ms_per_step": round(float(np.median(r["seg_ms"])), 4),
+        "segment_ms_per_step": [round(x, 4) for x in r["seg_ms"]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -532,8 +710,13 @@ def main():
         }
     if not args.no_multi:
         out["multi16"] = run_multi(args.steps_multi, 1)
+    if not args.no_extra:
+        out["config0"] = run_config0()
+        out["gradient"] = run_gradient()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(1, args.cpu_seconds, wl256)
+        if args.cpu_all_seconds > 0:
+            out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(args.cpu_all_seconds)
     print(json.dumps(out), flush=True)
 
 
