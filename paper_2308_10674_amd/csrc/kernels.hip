@@ -220,11 +220,15 @@ template <int N, int CB> struct ColG {
     // a lane pair of pass B (L = 2) is CB lanes apart and must share a wave
     static_assert(Fact<N>::L == 1 || 2 * CB <= kWave, "column tile too wide for lane pairs");
 };
+// OWN: probe elements of the block each thread owns (element k NT + tid),
+// so a tile may hold more probe rows than it has threads per row group.
 template <int N, int R_ = ITile<N>::R, int S_ = ITile<N>::S> struct InvG {
     static constexpr int N1 = Fact<N>::N1, N2 = Fact<N>::N2, T = N2;
     static constexpr int R = R_, S = S_;
     static constexpr int NT = S * R * T, GI = N / R;
-    static_assert(R * N <= NT && NT % kWave == 0 && N % R == 0 && (R * N) % kWave == 0, "inverse tile");
+    static constexpr int OWN = (R * N + NT - 1) / NT;
+    static_assert(NT % kWave == 0 && N % R == 0 && (R * N) % kWave == 0, "inverse tile");
+    static_assert(R * N <= NT || (R * N) % NT == 0, "owned probe elements");
 };
 
 // The maxima travel between stages as per-wave partials: the forward row
@@ -411,12 +415,17 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     const int rl = (threadIdx.x / g::T) % g::R;
     const int sl = threadIdx.x / (g::T * g::R);
     const int r = rb * g::R + rl;
-    // the element this thread owns in the probe block (if any)
-    const bool owner = threadIdx.x < g::R * N;
-    const int own_rl = owner ? threadIdx.x / N : 0, own_c = threadIdx.x % N;
-    const size_t own = (size_t)(rb * g::R + own_rl) * N + own_c;
-    const cf p_own = owner ? (MODE == kModeEpie ? ldc<COH>(&a.probe[own]) : a.gprobe[own]) : cf{0.f, 0.f};
-    cf acc = cf{0.f, 0.f};
+    // the elements this thread owns in the probe block: element
+    // e = k NT + threadIdx.x of the block's R rows (if e < R N)
+    constexpr int OWN = g::OWN;
+    cf p_own[OWN], acc[OWN];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        const int e = k * g::NT + (int)threadIdx.x;
+        const size_t own = (size_t)rb * g::R * N + e;
+        p_own[k] = e < g::R * N ? (MODE == kModeEpie ? ldc<COH>(&a.probe[own]) : a.gprobe[own]) : cf{0.f, 0.f};
+        acc[k] = cf{0.f, 0.f};
+    }
     if (a.bsize > 0) {
         const cf* prow = a.probe + (size_t)r * N;
         cf p[g::N1];
@@ -509,34 +518,43 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             __syncthreads();
             // slot order: this group's slots ascending, after the earlier groups
             const int nact = min(g::S, a.bsize - g0);
-            if (owner) {
+#pragma unroll
+            for (int k = 0; k < OWN; ++k) {
+                const int e = k * g::NT + (int)threadIdx.x;
+                if (e >= g::R * N) continue;
                 // the same sequential sum, with eight loads in flight at a time
-                const cf* col = dl + own_rl * N + own_c;
+                const cf* col = dl + e;
                 int q = 0;
                 for (; q + 8 <= nact; q += 8) {
                     cf tq[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) tq[u] = col[(size_t)(q + u) * g::R * N];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) acc = acc + tq[u];
+                    for (int u = 0; u < 8; ++u) acc[k] = acc[k] + tq[u];
                 }
-                for (; q < nact; ++q) acc = acc + col[(size_t)q * g::R * N];
+                for (; q < nact; ++q) acc[k] = acc[k] + col[(size_t)q * g::R * N];
             }
             __syncthreads();
         }
     }
-    if (MODE == kModeEpie) {
-        cf pn = p_own;
-        if (a.bsize > 0 && owner) {
-            pn = axpy(a.beta / (float)a.bsize, acc, p_own);
-            stc<COH>(&a.probe[own], pn);
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        const int e = k * g::NT + (int)threadIdx.x;
+        const bool owner = e < g::R * N;
+        const size_t own = (size_t)rb * g::R * N + e;
+        if (MODE == kModeEpie) {
+            cf pn = p_own[k];
+            if (a.bsize > 0 && owner) {
+                pn = axpy(a.beta / (float)a.bsize, acc[k], p_own[k]);
+                stc<COH>(&a.probe[own], pn);
+            }
+            // one partial per 64 consecutive elements of the block, from the
+            // wave that owns them (waves past R*N own none)
+            const float m = wave_max(norm2(pn));
+            if (threadIdx.x % kWave == 0 && owner) stc<COH>(&a.pmax_out[(rb * g::R * N + e) / kWave], m);
+        } else if (a.bsize > 0 && owner) {
+            a.gprobe[own] = p_own[k] + acc[k];
         }
-        // one partial per wave that owns probe elements (waves past R*N own none)
-        const float m = wave_max(norm2(pn));
-        if (threadIdx.x % kWave == 0 && threadIdx.x < g::R * N)
-            stc<COH>(&a.pmax_out[rb * (g::R * N / kWave) + threadIdx.x / kWave], m);
-    } else if (a.bsize > 0 && owner) {
-        a.gprobe[own] = p_own + acc;
     }
 }
 
@@ -653,7 +671,7 @@ constexpr int kMixRowNT = 256, kMixInvNT = 512;
 template <int N> struct MixTile;
 template <> struct MixTile<64>  { static constexpr int RB = 32, R = 4, S = 16, R2 = 8, S2 = 8; };
 template <> struct MixTile<128> { static constexpr int RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
-template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32, R2 = 2, S2 = 16; };
+template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
 template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
 template <int N> constexpr int kMixInvLds = MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE;
 template <int N> constexpr int kMixInvDl = MixTile<N>::S * MixTile<N>::R * N;
