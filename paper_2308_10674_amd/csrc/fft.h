@@ -154,11 +154,11 @@ template <int N1_, int N2_> struct FactL1 {
 };
 template <int N1_> struct FactL2 {
     static constexpr int N1 = N1_, N2 = 2 * N1_, L = 2;
-    static_assert(N2 == 16, "the pair twiddles are written for N2 = 16");
+    static_assert(N2 == 8 || N2 == 16, "the pair twiddles W_N2^k are taken from W_16");
     __host__ __device__ static inline int out(int t, int i) { return (t >> 1) + N1 * i + N1 * N1 * (t & 1); }
 };
 template <> struct Fact<16>  : FactL1<4, 4> {};
-template <> struct Fact<32>  : FactL1<8, 4> {};
+template <> struct Fact<32>  : FactL2<4> {};
 template <> struct Fact<64>  : FactL1<8, 8> {};
 template <> struct Fact<128> : FactL2<8> {};
 template <> struct Fact<256> : FactL1<16, 16> {};
@@ -285,7 +285,7 @@ __host__ __device__ inline void passB2_local(cf* v, const cf* z, int t) {
     dft<N1, DIR>(v);
     if (h) {
 #pragma unroll
-        for (int k = 1; k < N1; ++k) v[k] = w16<DIR>(v[k], k);
+        for (int k = 1; k < N1; ++k) v[k] = w16<DIR>(v[k], k * (16 / Fact<N>::N2));   // W_N2^k
     }
 }
 
@@ -309,7 +309,7 @@ __host__ __device__ inline void passB2inv_combine(cf* v, const cf* p, int t) {
     for (int i = 0; i < Fact<N>::N1; ++i) v[i] = p[i] + sg * v[i];
     if (t & 1) {
 #pragma unroll
-        for (int k = 1; k < Fact<N>::N1; ++k) v[k] = w16<DIR>(v[k], k);
+        for (int k = 1; k < Fact<N>::N1; ++k) v[k] = w16<DIR>(v[k], k * (16 / Fact<N>::N2));   // W_N2^k
     }
 }
 
@@ -340,7 +340,16 @@ __host__ __device__ inline void passAinv_from_lds(cf* v, const cf* z, int t) {
 template <int XOR>
 __device__ inline cf lane_swap(cf v) {
     static_assert(XOR > 0 && XOR < 64 && (XOR & (XOR - 1)) == 0, "lane distance");
-    return cf{__shfl_xor(v.x, XOR, 64), __shfl_xor(v.y, XOR, 64)};
+    if constexpr (XOR == 1 || XOR == 2) {
+        // neighbours within a quad: a DPP quad permutation ([1,0,3,2] or
+        // [2,3,0,1]), a modifier of a VALU move instead of a trip through
+        // the LDS crossbar
+        constexpr int ctrl = XOR == 1 ? 0xB1 : 0x4E;
+        return cf{__int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.x), ctrl, 0xF, 0xF, false)),
+                  __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.y), ctrl, 0xF, 0xF, false))};
+    } else {
+        return cf{__shfl_xor(v.x, XOR, 64), __shfl_xor(v.y, XOR, 64)};
+    }
 }
 
 template <int N, int DIR, int XOR>

@@ -972,10 +972,21 @@ template <int N> constexpr int kStrictLdsBase =
     (int)sizeof(cf) * (N * N + N * kStrictTP<N> + N * Lds<N>::LINE) + kStrictNW<N> * (2 * 4 + 8) + 64;
 template <int N> constexpr int kStrictObj = (160 * 1024 - kStrictLdsBase<N>) / (int)sizeof(cf);
 
+// The N2 threads of one transform line are lanes of one wave, so the LDS
+// exchange between the passes of a line needs only a wave-level ordering:
+// a wave's LDS operations execute in issue order, and the fences keep the
+// compiler from moving them across this point.
+__device__ __forceinline__ void line_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int N, bool OL>
 __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count) {
     using F = Fact<N>;
     constexpr int N1 = F::N1, N2 = F::N2, NT = kStrictNT<N>, TP = kStrictTP<N>, NW = kStrictNW<N>;
+    static_assert(kWave % N2 == 0, "a transform line lies within one wave");
     __shared__ cf P[N * N];
     __shared__ cf tile[N * TP];
     __shared__ cf line[N * Lds<N>::LINE];
@@ -1045,7 +1056,7 @@ __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count)
         for (int i = 0; i < N1; ++i) valid[i] = a.mask == nullptr || a.mask[F::out(t, i) * N + l] != 0;
         // row pass (forward): spectrum row l into the tile
         passA_to_lds<N, -1>(v, z, t, wa);
-        __syncthreads();
+        line_sync();
         passB_from_lds<N, -1, 1>(v, z, t);
 #pragma unroll
         for (int i = 0; i < N1; ++i) tile[l * TP + F::out(t, i)] = v[i];
@@ -1054,7 +1065,7 @@ __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count)
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) v[n1] = tile[(N2 * n1 + t) * TP + l];
         passA_to_lds<N, -1>(v, z, t, wa);
-        __syncthreads();
+        line_sync();
         passB_from_lds<N, -1, 1>(v, z, t);
         float err = 0.f;
 #pragma unroll
@@ -1067,9 +1078,9 @@ __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count)
             const float f = mag > 0.f ? amp[i] / mag : 0.f;
             v[i] = f * zz;
         }
-        __syncthreads();
+        line_sync();
         passBinv_to_lds<N, +1, 1>(v, z, t, wb);
-        __syncthreads();
+        line_sync();
         passAinv_from_lds<N, +1>(v, z, t);
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) tile[(N2 * n1 + t) * TP + l] = v[n1];
@@ -1087,7 +1098,7 @@ __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count)
 #pragma unroll
         for (int i = 0; i < N1; ++i) v[i] = tile[l * TP + F::out(t, i)];
         passBinv_to_lds<N, +1, 1>(v, z, t, wb);
-        __syncthreads();
+        line_sync();
         passAinv_from_lds<N, +1>(v, z, t);
         const float ostep = a.alpha / pm;
         const float pstep = 1.f / om;
