@@ -94,6 +94,16 @@ __device__ inline double wave_sum(double v) {
     return (lane_of(v, 0) + lane_of(v, 16)) + (lane_of(v, 32) + lane_of(v, 48));
 }
 
+// The N2 threads of one transform line are lanes of one wave, so the LDS
+// exchange between the passes of a line needs only a wave-level ordering:
+// a wave's LDS operations execute in issue order, and the fences keep the
+// compiler from moving them across this point.
+__device__ __forceinline__ void line_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // block-wide sum in a fixed order; the result is valid in thread 0
 template <int NT>
 __device__ inline double block_sum(double v, double* sh) {
@@ -323,7 +333,7 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
     }
     cf* z = lds + rl * Lds<N>::LINE;
     passA_to_lds<N, -1>(v, z, t, w);
-    __syncthreads();
+    line_sync();   // row rl's threads are consecutive lanes of one wave
     passB_from_lds<N, -1, 1>(v, z, t);
     cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
 #pragma unroll
@@ -485,7 +495,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 wpart[k] = MODE == kModeEpie && i < kWinParts<N> ? ldc<COH>(&a.winmax[ws * kWinParts<N> + i]) : 0.f;
             }
             passBinv_to_lds<N, +1, 1>(v, z, t, wb);
-            __syncthreads();
+            line_sync();   // the line's threads are consecutive lanes of one wave
             passAinv_from_lds<N, +1>(v, z, t);
             if (MODE == kModeEpie) {
                 float wm = 0.f;
@@ -971,16 +981,6 @@ template <int N> constexpr int kStrictNW = kStrictNT<N> / kWave > 0 ? kStrictNT<
 template <int N> constexpr int kStrictLdsBase =
     (int)sizeof(cf) * (N * N + N * kStrictTP<N> + N * Lds<N>::LINE) + kStrictNW<N> * (2 * 4 + 8) + 64;
 template <int N> constexpr int kStrictObj = (160 * 1024 - kStrictLdsBase<N>) / (int)sizeof(cf);
-
-// The N2 threads of one transform line are lanes of one wave, so the LDS
-// exchange between the passes of a line needs only a wave-level ordering:
-// a wave's LDS operations execute in issue order, and the fences keep the
-// compiler from moving them across this point.
-__device__ __forceinline__ void line_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int N, bool OL>
 __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count) {
