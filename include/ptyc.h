@@ -352,11 +352,13 @@ const char* ptyc_init_error(void);
  * for real functions of complex variables (dL/dRe + i dL/dIm):
  *   g_Psi = 2 (|Psi| - sqrt I) sgn(Psi), g_psi = F^H g_Psi,
  *   dL/dO[window j] += conj(P) g_psi,  dL/dP += conj(S_j O) g_psi.
- * The forward transforms of the whole minibatch run at once; overlapping
- * windows are accumulated into dL/dO in a fixed order (the minibatch is
- * split into batches of disjoint windows, taken one after another), so
- * the result is deterministic.  Work buffers grow to the minibatch size
- * (N^2 complex64 per position).  Synchronises the stream.  Errors:
+ * The whole minibatch is transformed at once (forward and adjoint); the
+ * contributions of overlapping windows to dL/dO and those of all positions
+ * to dL/dP are then summed in a fixed order (minibatch order for every
+ * object pixel; dL/dP in groups of 16 consecutive positions, then over the
+ * groups), so the result is deterministic.  Work buffers grow to the
+ * minibatch size (about N^2 complex64 per position).  Synchronises the
+ * stream.  Errors:
  * PTYC_ERR_ARG for NULL buffers, an index that is not loaded, only one
  * gradient buffer, a non-finite scale. */
 int ptyc_amp_loss(ptyc_ctx* ctx, const void* obj, const void* probe, const int64_t* idx,

@@ -101,6 +101,7 @@ struct ptyc_ctx {
     DevBuf mask;                     // uint8 [n][n] measured detector pixels (stored layout), if set
     ptyc_ingest ingest{};            // how raw frames become stored amplitudes
     DevBuf staging;                  // host intensities staged on the device
+    DevBuf gpart;                    // amplitude-loss adjoint: partial sums of dL/dP
 
     // host state
     std::vector<int32_t> h_pos;      // 2 per position
@@ -448,7 +449,7 @@ void ptyc_destroy(ptyc_ctx* c) {
     DevBuf* bufs[] = {&c->obj, &c->probe, &c->tw, &c->sqrt_i, &c->pos, &c->sum_i, &c->scratch,
                       &c->winmax, &c->pmax_part, &c->order, &c->offs, &c->err_part,
                       &c->err_dev, &c->bad, &c->sync, &c->multi, &c->mask, &c->staging,
-                      &c->gorder, &c->goffs, &c->tune_save, &c->mbar};
+                      &c->gorder, &c->goffs, &c->tune_save, &c->mbar, &c->gpart};
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->mgexec) (void)hipGraphExecDestroy(c->mgexec);
     for (DevBuf* b : bufs) release(*b);
@@ -1517,10 +1518,12 @@ namespace {
 
 // The amplitude loss (and its gradient) of a minibatch, enqueued on the
 // context's stream: the forward stages over the whole minibatch in one
-// launch pair (they write nothing but the exchange and the loss partials),
-// then, for the gradient, the adjoint's row stage once per batch of
-// disjoint windows (overlapping windows accumulate into dL/dO one batch
-// after another, a fixed order); the loss sum lands in loss_dev.
+// launch pair (they write nothing but the exchange and the loss partials);
+// for the gradient, one adjoint row launch over the whole minibatch leaves
+// every position's contributions to dL/dO and dL/dP in work buffers, which
+// two sums in minibatch order reduce (dL/dP over slots, dL/dO by object
+// tiles, each tile over the positions whose windows cover it), so the
+// result does not depend on timing.  The loss sum lands in loss_dev.
 int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int64_t* idx, int64_t count,
                      float grad_scale, void* grad_obj, void* grad_probe, double* loss_dev) {
     if (!obj || !probe) return fail(c, PTYC_ERR_ARG, "obj and probe must not be NULL");
@@ -1534,25 +1537,38 @@ int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int6
     int rc;
     const bool grad = grad_obj != nullptr;
     const int n = c->cfg.n;
+    const int64_t h = c->cfg.h, w = c->cfg.w;
     const size_t nn = (size_t)n * n;
+    if (grad && count == 0) HIPCHK(c, launch_fill_zero(grad_probe, (int64_t)nn, c->stream));
+    // dL/dO by object tiles: for every tile of the object, the slots whose
+    // windows cover it in ascending order (compressed rows: tile_off, tile_slot)
+    const int tiles_y = (int)((h + kGradTR - 1) / kGradTR), tiles_x = (int)((w + kGradTC - 1) / kGradTC);
+    const size_t n_tiles = (size_t)tiles_y * tiles_x;
+    std::vector<int32_t> tile_off, tile_slot;
     if (grad) {
-        HIPCHK(c, launch_fill_zero(grad_obj, (int64_t)c->cfg.h * c->cfg.w, c->stream));
-        HIPCHK(c, launch_fill_zero(grad_probe, (int64_t)nn, c->stream));
-    }
-    // batches of disjoint windows inside the minibatch (greedy, in list
-    // order); the forward stages run over the concatenation at once
-    std::vector<int32_t> mp((size_t)(2 * count));
-    for (int64_t i = 0; i < count; ++i) {
-        mp[(size_t)(2 * i)] = c->h_pos[(size_t)(2 * idx[i])];
-        mp[(size_t)(2 * i + 1)] = c->h_pos[(size_t)(2 * idx[i] + 1)];
-    }
-    Colouring col(n, max_batch_of(c));
-    col.extend(mp.data(), 0, count);
-    std::vector<int64_t> order, off{0};
-    order.reserve((size_t)count);
-    for (const auto& m : col.members()) {
-        for (int64_t k : m) order.push_back(idx[k]);
-        off.push_back((int64_t)order.size());
+        auto span = [&](int64_t i, int& ty0, int& ty1, int& tx0, int& tx1) {
+            const int32_t row = c->h_pos[(size_t)(2 * idx[i])], col = c->h_pos[(size_t)(2 * idx[i] + 1)];
+            ty0 = row / kGradTR;
+            ty1 = (row + n - 1) / kGradTR;
+            tx0 = col / kGradTC;
+            tx1 = (col + n - 1) / kGradTC;
+        };
+        tile_off.assign(n_tiles + 1, 0);
+        for (int64_t i = 0; i < count; ++i) {
+            int ty0, ty1, tx0, tx1;
+            span(i, ty0, ty1, tx0, tx1);
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) ++tile_off[(size_t)ty * tiles_x + tx + 1];
+        }
+        for (size_t t = 0; t < n_tiles; ++t) tile_off[t + 1] += tile_off[t];
+        std::vector<int32_t> fill(tile_off.begin(), tile_off.end() - 1);
+        tile_slot.resize((size_t)tile_off.back());
+        for (int64_t i = 0; i < count; ++i) {
+            int ty0, ty1, tx0, tx1;
+            span(i, ty0, ty1, tx0, tx1);
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) tile_slot[(size_t)fill[(size_t)ty * tiles_x + tx]++] = (int32_t)i;
+        }
     }
     const int64_t slots = std::max<int64_t>(count, 1);
     if (slots > c->slots) {
@@ -1560,47 +1576,55 @@ int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int6
         if ((rc = ensure(c, c->winmax, (size_t)slots * max_row_blocks(c) * sizeof(float))) != PTYC_OK) return rc;
         c->slots = slots;
     }
+    const int64_t parts = (count + kAdjGroup - 1) / kAdjGroup;   // partial sums of dL/dP
+    if (grad && count > 0 && (rc = ensure(c, c->gpart, (size_t)parts * nn * sizeof(cf))) != PTYC_OK) return rc;
+    // one upload: the order entries, then the tile lists
     const size_t obytes = (size_t)count * sizeof(OrderEntry);
+    const size_t tbytes = (tile_off.size() + tile_slot.size()) * sizeof(int32_t);
+    const size_t ubytes = obytes + tbytes;
     // the pinned upload buffer may still feed an earlier copy
     if (c->upload_pending) {
         HIPCHK(c, hipEventSynchronize(c->upload_done));
         c->upload_pending = false;
     }
-    if ((rc = ensure(c, c->order, std::max<size_t>(obytes, sizeof(OrderEntry)))) != PTYC_OK) return rc;
+    if ((rc = ensure(c, c->order, std::max<size_t>(ubytes, sizeof(OrderEntry)))) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->err_part, (size_t)slots * c->sb.col_blocks * sizeof(double))) != PTYC_OK) return rc;
-    if (c->pinned_bytes < obytes) {
+    if (c->pinned_bytes < ubytes) {
         if (c->pinned_order) (void)hipHostFree(c->pinned_order);
         c->pinned_order = nullptr;
         c->pinned_bytes = 0;
-        hipError_t e = hipHostMalloc((void**)&c->pinned_order, obytes, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void**)&c->pinned_order, ubytes, hipHostMallocDefault);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(c, PTYC_ERR_OOM, "pinned host allocation failed");
         }
-        c->pinned_bytes = obytes;
+        c->pinned_bytes = ubytes;
     }
-    if (count > 0) {
-        to_entries(c, order.data(), count, (OrderEntry*)c->pinned_order);
-        HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, obytes, hipMemcpyHostToDevice, c->stream));
+    const int32_t* d_tile_off = (const int32_t*)((const char*)c->order.p + obytes);
+    const int32_t* d_tile_slot = d_tile_off + tile_off.size();
+    if (ubytes > 0) {
+        to_entries(c, idx, count, (OrderEntry*)c->pinned_order);
+        int32_t* pt = (int32_t*)((char*)c->pinned_order + obytes);
+        std::copy(tile_off.begin(), tile_off.end(), pt);
+        std::copy(tile_slot.begin(), tile_slot.end(), pt + tile_off.size());
+        HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, ubytes, hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
         c->upload_pending = true;
     }
     BatchArgs a = base_args(c);
     a.obj = (cf*)obj;
     a.probe = (cf*)probe;
-    a.gobj = (cf*)grad_obj;
-    a.gprobe = (cf*)grad_probe;
     a.gscale = grad_scale;
     a.off = 0;
     a.bsize = (int)count;
     HIPCHK(c, launch_loss_fwd(n, a, grad, c->stream));
     if (grad) {
-        for (size_t b = 0; b + 1 < off.size(); ++b) {
-            a.off = off[b];
-            a.bsize = (int)(off[b + 1] - off[b]);
-            a.scratch = (cf*)c->scratch.p + (size_t)off[b] * nn;
-            HIPCHK(c, launch_grad_rows(n, a, c->stream));
+        if (count > 0) {
+            HIPCHK(c, launch_adjoint_rows(n, a, c->gpart.p, c->stream));
+            HIPCHK(c, launch_probe_grad_sum(c->gpart.p, (int64_t)nn, (int)parts, grad_probe, c->stream));
         }
+        HIPCHK(c, launch_obj_grad_gather(c->scratch.p, (const OrderEntry*)c->order.p, n, h, w, d_tile_off, d_tile_slot,
+                                         grad_obj, c->stream));
     }
     HIPCHK(c, launch_sum_reduce((const double*)c->err_part.p, count * c->sb.col_blocks, loss_dev, c->stream));
     return PTYC_OK;

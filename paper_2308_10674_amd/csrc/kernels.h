@@ -36,9 +36,7 @@ struct BatchArgs {
     float* pmax_out;          // [Shape::probe_blocks]
     double* err_part;         // [order_len][column blocks] error partial sums
     float alpha, beta;
-    cf* gobj;                 // amplitude-loss gradient w.r.t. the object (accumulated)
-    cf* gprobe;               // amplitude-loss gradient w.r.t. the probe (accumulated)
-    float gscale;             // upstream scale of the gradient
+    float gscale;             // upstream scale of the amplitude-loss gradient
     const unsigned char* mask;  // [n][n] 1 = measured detector pixel; nullptr: all measured
     const int64_t* boffs;     // graph nodes: off and bsize are read from boffs[batch], boffs[batch + 1]
     int batch;
@@ -149,12 +147,26 @@ hipError_t build_sweep_graph(int n, int variant, const BatchArgs& a, int nb, int
 // Amplitude loss, forward stages over a.bsize positions a.order[a.off ..]
 // (windows may overlap), slot k's spectrum at a.scratch + k N^2; loss
 // partials into a.err_part; grad: the column stage leaves dL/dpsi's row
-// transforms in the exchange for launch_grad_rows.
+// transforms in the exchange for launch_adjoint_rows.
 hipError_t launch_loss_fwd(int n, const BatchArgs& a, bool grad, hipStream_t s);
-// the adjoint's row stage for one batch of disjoint windows (a.scratch
-// pointing at the batch's first slot): accumulates dL/dO into gobj and
-// dL/dP into gprobe
-hipError_t launch_grad_rows(int n, const BatchArgs& a, hipStream_t s);
+// The adjoint over the same a.bsize positions after launch_loss_fwd(grad):
+// the inverse row transforms give dL/dpsi of every position; its
+// contribution conj(P) dL/dpsi to dL/dO replaces the position's spectrum in
+// a.scratch, and the sums of conj(S_j O) dL/dpsi over each group of
+// kAdjGroup consecutive positions go to part ([groups][n][n] complex64,
+// groups = ceil(bsize / kAdjGroup)).
+constexpr int kAdjGroup = 16, kAdjLanes = 4;
+hipError_t launch_adjoint_rows(int n, const BatchArgs& a, void* part, hipStream_t s);
+// dL/dP = the `parts` partial sums (nn complex64 each) added in order, into gprobe
+hipError_t launch_probe_grad_sum(const void* part, int64_t nn, int parts, void* gprobe, hipStream_t s);
+// dL/dO over the whole h x w object by tiles of kGradTR x kGradTC pixels
+// (row-major tile index t, ceil(w / kGradTC) tiles per row): tile t sums
+// the contributions co_slot of the slots tile_slot[tile_off[t] ..
+// tile_off[t + 1]) (ascending) over the pixels each window covers and
+// writes every pixel of the tile to gobj
+constexpr int kGradTR = 16, kGradTC = 64;
+hipError_t launch_obj_grad_gather(const void* co_slot, const OrderEntry* order, int n, int64_t h, int64_t w,
+                                  const int* tile_off, const int* tile_slot, void* gobj, hipStream_t s);
 // multiply count complex values in place by the device scalar *scale
 hipError_t launch_scale(void* p, int64_t count_c64, const double* scale, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s);

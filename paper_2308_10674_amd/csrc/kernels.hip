@@ -418,7 +418,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 // conj(S_j O) Delta / max|S_j O|^2 summed over slots in slot order, then
 // P_{b+1} written for the block.  bsize == 0 only refreshes the block's
 // max |P|^2.
-template <int N, int R, int S, int MODE = kModeEpie, bool COH = false>
+template <int N, int R, int S, bool COH = false>
 __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl) {
     using g = InvG<N, R, S>;
     const int t = threadIdx.x % g::T;
@@ -433,7 +433,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     for (int k = 0; k < OWN; ++k) {
         const int e = k * g::NT + (int)threadIdx.x;
         const size_t own = (size_t)rb * g::R * N + e;
-        p_own[k] = e < g::R * N ? (MODE == kModeEpie ? ldc<COH>(&a.probe[own]) : a.gprobe[own]) : cf{0.f, 0.f};
+        p_own[k] = e < g::R * N ? ldc<COH>(&a.probe[own]) : cf{0.f, 0.f};
         acc[k] = cf{0.f, 0.f};
     }
     if (a.bsize > 0) {
@@ -441,18 +441,15 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         cf p[g::N1];
 #pragma unroll
         for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = ldc<COH>(&prow[g::N2 * n1 + t]);
-        float ostep = 0.f;
-        if (MODE == kModeEpie) {
-            // every wave reduces all partial maxima itself (no barrier)
-            float pm = 0.f;
+        // every wave reduces all partial maxima itself (no barrier)
+        float pm = 0.f;
 #pragma unroll
-            for (int k = 0; k < (kProbeParts<N> + kWave - 1) / kWave; ++k) {
-                const int i = k * kWave + (int)(threadIdx.x % kWave);
-                if (i < kProbeParts<N>) pm = fmaxf(pm, ldc<COH>(&a.pmax_in[i]));
-            }
-            pm = wave_max(pm);
-            ostep = a.alpha / pm;
+        for (int k = 0; k < (kProbeParts<N> + kWave - 1) / kWave; ++k) {
+            const int i = k * kWave + (int)(threadIdx.x % kWave);
+            if (i < kProbeParts<N>) pm = fmaxf(pm, ldc<COH>(&a.pmax_in[i]));
         }
+        pm = wave_max(pm);
+        const float ostep = a.alpha / pm;
         // twiddles ahead of the slot loads: the transform then waits for
         // them and the spectrum row only (loads complete in issue order)
         cf wb[g::N1];
@@ -492,37 +489,25 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
 #pragma unroll
             for (int k = 0; k < kWm; ++k) {
                 const int i = k * GT + (int)(threadIdx.x % GT);
-                wpart[k] = MODE == kModeEpie && i < kWinParts<N> ? ldc<COH>(&a.winmax[ws * kWinParts<N> + i]) : 0.f;
+                wpart[k] = i < kWinParts<N> ? ldc<COH>(&a.winmax[ws * kWinParts<N> + i]) : 0.f;
             }
             passBinv_to_lds<N, +1, 1>(v, z, t, wb);
             line_sync();   // the line's threads are consecutive lanes of one wave
             passAinv_from_lds<N, +1>(v, z, t);
-            if (MODE == kModeEpie) {
-                float wm = 0.f;
+            float wm = 0.f;
 #pragma unroll
-                for (int k = 0; k < kWm; ++k) wm = fmaxf(wm, wpart[k]);
-                wm = group_max<GT>(wm);
-                if (act) om = wm;
-            }
+            for (int k = 0; k < kWm; ++k) wm = fmaxf(wm, wpart[k]);
+            wm = group_max<GT>(wm);
+            if (act) om = wm;
             constexpr float inv = 1.0f / (float)(N * N);
             const float pstep = 1.f / om;
-            if (act && MODE == kModeEpie) {
+            if (act) {
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     const int col = g::N2 * n1 + t;
                     const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
                     store_through(&orow[col], axpy(ostep, cmulc(p[n1], delta), o[n1]));
                     drow[col] = pstep * cmulc(o[n1], delta);
-                }
-            } else if (act) {
-                // v = F^H g_Psi = dL/dpsi: dL/dO on the window += conj(P) g, dL/dP += conj(S_j O) g
-                const OrderEntry e = a.order[a.off + slot];
-                cf* grow = a.gobj + (size_t)(e.row + r) * a.w + e.col;
-#pragma unroll
-                for (int n1 = 0; n1 < g::N1; ++n1) {
-                    const int col = g::N2 * n1 + t;
-                    grow[col] = grow[col] + cmulc(p[n1], v[n1]);
-                    drow[col] = cmulc(o[n1], v[n1]);
                 }
             }
             __syncthreads();
@@ -552,19 +537,15 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         const int e = k * g::NT + (int)threadIdx.x;
         const bool owner = e < g::R * N;
         const size_t own = (size_t)rb * g::R * N + e;
-        if (MODE == kModeEpie) {
-            cf pn = p_own[k];
-            if (a.bsize > 0 && owner) {
-                pn = axpy(a.beta / (float)a.bsize, acc[k], p_own[k]);
-                stc<COH>(&a.probe[own], pn);
-            }
-            // one partial per 64 consecutive elements of the block, from the
-            // wave that owns them (waves past R*N own none)
-            const float m = wave_max(norm2(pn));
-            if (threadIdx.x % kWave == 0 && owner) stc<COH>(&a.pmax_out[(rb * g::R * N + e) / kWave], m);
-        } else if (a.bsize > 0 && owner) {
-            a.gprobe[own] = p_own[k] + acc[k];
+        cf pn = p_own[k];
+        if (a.bsize > 0 && owner) {
+            pn = axpy(a.beta / (float)a.bsize, acc[k], p_own[k]);
+            stc<COH>(&a.probe[own], pn);
         }
+        // one partial per 64 consecutive elements of the block, from the
+        // wave that owns them (waves past R*N own none)
+        const float m = wave_max(norm2(pn));
+        if (threadIdx.x % kWave == 0 && owner) stc<COH>(&a.pmax_out[(rb * g::R * N + e) / kWave], m);
     }
 }
 
@@ -772,8 +753,8 @@ __global__ __launch_bounds__(256) void k_mean(MeanArgs m) {
     }
 }
 
-// Amplitude-loss forward (MODE kModeLoss: rows_fwd + cols only) and its
-// adjoint (kModeGrad: rows_fwd, cols, rows_inv accumulating the gradients).
+// The column stage of the amplitude loss (kModeLoss: loss partials only) or
+// of its gradient (kModeGrad: also g_Psi, transformed back along columns).
 template <int N, int MODE>
 __global__ __launch_bounds__(kColNT<N>) void k_cols_mode(BatchArgs a) {
     constexpr int CB = Tile<N>::CB;
@@ -783,12 +764,148 @@ __global__ __launch_bounds__(kColNT<N>) void k_cols_mode(BatchArgs a) {
     stage_cols<N, CB, MODE>(a, blockIdx.x / g::GC, blockIdx.x % g::GC, lds, red);
 }
 
-template <int N, int R = ITile<N>::R, int S = ITile<N>::S>
-__global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_grad(BatchArgs a) {
-    using g = InvG<N, R, S>;
-    __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
-    __shared__ cf dl[g::S * g::R * N];
-    stage_rows_inv<N, g::R, g::S, kModeGrad>(a, blockIdx.x, lds, dl);
+// ---------------------------------------------------------------- amplitude-loss adjoint
+// dL/dpsi of every position of a minibatch at once.  A workgroup takes AR
+// rows of the slots of one group of kAdjGroup consecutive slots, kAdjLanes
+// slots at a time (one 64-thread lane set per slot): the inverse row FFT of
+// the column stage's output gives F^H g_Psi (unscaled, = dL/dpsi); the
+// position's contribution conj(P) dL/dpsi to dL/dO on its window replaces
+// the slot's spectrum rows (windows may overlap: the object tiles sum them
+// afterwards), and conj(S_j O) dL/dpsi is added to the lane set's running
+// dL/dP rows, which are combined in lane order at the end into the group's
+// partial sum part[group] (summed over the groups in order afterwards).
+template <int N> struct AdjG {
+    static constexpr int T = Fact<N>::N2, AR = kWave / T;   // one wave per slot and row block
+    using rg = RowG<N, AR>;
+    static constexpr int G = rg::G, NT = kAdjLanes * kWave;
+};
+
+template <int N>
+__global__ __launch_bounds__(kAdjLanes * kWave) void k_rows_adj(BatchArgs a, cf* part) {
+    using ag = AdjG<N>;
+    using g = typename ag::rg;
+    constexpr int AR = ag::AR;
+    __shared__ cf lds[kAdjLanes * AR * Lds<N>::LINE];
+    static_assert(Lds<N>::LINE >= N, "the lines hold the lane sets' partial sums afterwards");
+    cf* red = lds;   // after the loop: lane set k > 0's dL/dP rows at [(k - 1) AR + row] N
+    const int grp = blockIdx.x / ag::G, rb = blockIdx.x % ag::G;
+    const int t = threadIdx.x % g::T, rl = (threadIdx.x / g::T) % AR, ln = threadIdx.x / kWave;
+    const int r = rb * AR + rl;
+    cf wb[g::N1];
+    twiddles_binv<N, +1>(wb, t, a.tw);
+    const cf* prow = a.probe + (size_t)r * N;
+    cf p[g::N1], acc[g::N1];
+#pragma unroll
+    for (int n1 = 0; n1 < g::N1; ++n1) {
+        p[n1] = prow[g::N2 * n1 + t];
+        acc[n1] = cf{0.f, 0.f};
+    }
+    cf* z = lds + (ln * AR + rl) * Lds<N>::LINE;
+    const int s1 = min(a.bsize, (grp + 1) * kAdjGroup);
+    for (int slot = grp * kAdjGroup + ln; slot < s1; slot += kAdjLanes) {
+        cf* srow = a.scratch + (size_t)slot * N * N + (size_t)r * N;
+        cf v[g::N1], o[g::N1];
+#pragma unroll
+        for (int i = 0; i < g::N1; ++i) v[i] = srow[Fact<N>::out(t, i)];
+        const OrderEntry e = a.order[a.off + slot];
+        const cf* orow = a.obj + (size_t)(e.row + r) * a.w + e.col;
+#pragma unroll
+        for (int n1 = 0; n1 < g::N1; ++n1) o[n1] = orow[g::N2 * n1 + t];
+        passBinv_to_lds<N, +1, 1>(v, z, t, wb);
+        line_sync();   // the line's threads are consecutive lanes of one wave
+        passAinv_from_lds<N, +1>(v, z, t);
+        // the row's spectrum was read by this wave before the transform, so
+        // the contribution may replace it
+#pragma unroll
+        for (int n1 = 0; n1 < g::N1; ++n1) {
+            const int col = g::N2 * n1 + t;
+            srow[col] = cmulc(p[n1], v[n1]);
+            acc[n1] = acc[n1] + cmulc(o[n1], v[n1]);
+        }
+        line_sync();   // the next slot's transform reuses the line
+    }
+    __syncthreads();   // every lane set is done with its lines
+    if (ln > 0) {
+#pragma unroll
+        for (int n1 = 0; n1 < g::N1; ++n1) red[((ln - 1) * AR + rl) * N + g::N2 * n1 + t] = acc[n1];
+    }
+    __syncthreads();
+    if (ln == 0) {
+        cf* prt = part + (size_t)grp * N * N + (size_t)r * N;
+#pragma unroll
+        for (int n1 = 0; n1 < g::N1; ++n1) {
+            const int col = g::N2 * n1 + t;
+            cf sum = acc[n1];
+#pragma unroll
+            for (int k = 1; k < kAdjLanes; ++k) sum = sum + red[((k - 1) * AR + rl) * N + col];
+            prt[col] = sum;
+        }
+    }
+}
+
+// dL/dP: the groups' partial sums added in group order, eight loads in
+// flight at a time
+__global__ __launch_bounds__(256) void k_probe_grad_sum(const cf* part, int64_t nn, int parts, cf* gprobe) {
+    const int64_t el = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (el >= nn) return;
+    cf acc = cf{0.f, 0.f};
+    int q = 0;
+    for (; q + 8 <= parts; q += 8) {
+        cf tq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tq[u] = part[(size_t)(q + u) * nn + el];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = acc + tq[u];
+    }
+    for (; q < parts; ++q) acc = acc + part[(size_t)q * nn + el];
+    gprobe[el] = acc;
+}
+
+// dL/dO by object tiles of kGradTR x kGradTC pixels, one workgroup per
+// tile: each pixel of the tile gets the sum of the contributions of the
+// windows that cover it, over the slots listed for the tile (ascending), and
+// every pixel is written (zero where no window reaches).
+__global__ __launch_bounds__(256) void k_obj_grad_gather(const cf* co_slot, const OrderEntry* order, int n,
+                                                        int64_t h, int64_t w, int tiles_x, const int* tile_off,
+                                                        const int* tile_slot, cf* gobj) {
+    constexpr int kRowsPerPass = 256 / kGradTC, KR = kGradTR / kRowsPerPass, U = 8;
+    const int tid = (int)blockIdx.x;
+    const int64_t y0 = (int64_t)(tid / tiles_x) * kGradTR, x0 = (int64_t)(tid % tiles_x) * kGradTC;
+    const int cx = (int)threadIdx.x % kGradTC, ry = (int)threadIdx.x / kGradTC;
+    const int64_t x = x0 + cx;
+    const int64_t nn = (int64_t)n * n;
+    cf acc[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) acc[k] = cf{0.f, 0.f};
+    const int q1 = tile_off[tid + 1];
+    // U slots at a time, so their loads are in flight together; the sum
+    // still runs over the slots in ascending order (a pixel outside a
+    // window adds zero, which changes no sum)
+    for (int q0 = tile_off[tid]; q0 < q1; q0 += U) {
+        cf c[U][KR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool live = q0 + u < q1;
+            const int s = live ? tile_slot[q0 + u] : 0;
+            const OrderEntry e = order[s];
+            const int64_t dx = x - e.col;
+            const bool in_x = live && dx >= 0 && dx < n;
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int64_t dy = y0 + ry + (int64_t)k * kRowsPerPass - e.row;
+                c[u][k] = in_x && dy >= 0 && dy < n ? co_slot[(size_t)s * nn + dy * n + dx] : cf{0.f, 0.f};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < KR; ++k) acc[k] = acc[k] + c[u][k];
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int64_t y = y0 + ry + (int64_t)k * kRowsPerPass;
+        if (y < h && x < w) gobj[y * w + x] = acc[k];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_zero(cf* p, int64_t n) {
@@ -879,7 +996,7 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
                 stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds, red);
             target += (unsigned)sc.gn;
             if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
-            for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, kModeEpie, true>(a, it, lds, dl);
+            for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, true>(a, it, lds, dl);
             target += (unsigned)sc.gn;
             if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
             // the maxima just written are those of the next batch's probe
@@ -1356,11 +1473,11 @@ hipError_t loss_fwd_n(const BatchArgs& a, bool grad, hipStream_t s) {
     return hipGetLastError();
 }
 
-// the adjoint's row stage for one batch of disjoint windows
 template <int N>
-hipError_t grad_rows_n(const BatchArgs& a, hipStream_t s) {
+hipError_t adjoint_rows_n(const BatchArgs& a, cf* part, hipStream_t s) {
     if (a.bsize <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rows_grad<N>, dim3(InvG<N>::GI), dim3(InvG<N>::NT), 0, s, a);
+    const int groups = (a.bsize + kAdjGroup - 1) / kAdjGroup;
+    hipLaunchKernelGGL(k_rows_adj<N>, dim3(AdjG<N>::G * groups), dim3(AdjG<N>::NT), 0, s, a, part);
     return hipGetLastError();
 }
 
@@ -1593,9 +1710,23 @@ hipError_t launch_loss_fwd(int n, const BatchArgs& a, bool grad, hipStream_t s) 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_grad_rows(int n, const BatchArgs& a, hipStream_t s) {
-    PTYC_DISPATCH(n, grad_rows_n<N>(a, s));
+hipError_t launch_adjoint_rows(int n, const BatchArgs& a, void* part, hipStream_t s) {
+    PTYC_DISPATCH(n, adjoint_rows_n<N>(a, (cf*)part, s));
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_probe_grad_sum(const void* part, int64_t nn, int parts, void* gprobe, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe_grad_sum, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, (const cf*)part, nn,
+                       parts, (cf*)gprobe);
+    return hipGetLastError();
+}
+
+hipError_t launch_obj_grad_gather(const void* co_slot, const OrderEntry* order, int n, int64_t h, int64_t w,
+                                  const int* tile_off, const int* tile_slot, void* gobj, hipStream_t s) {
+    const int tiles_x = (int)((w + kGradTC - 1) / kGradTC), tiles_y = (int)((h + kGradTR - 1) / kGradTR);
+    hipLaunchKernelGGL(k_obj_grad_gather, dim3((unsigned)(tiles_x * tiles_y)), dim3(256), 0, s, (const cf*)co_slot,
+                       order, n, h, w, tiles_x, tile_off, tile_slot, (cf*)gobj);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale(void* p, int64_t count_c64, const double* scale, hipStream_t s) {
