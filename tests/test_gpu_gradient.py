@@ -276,3 +276,48 @@ def test_bad_arguments(problem, torch_cuda):
     with pytest.raises(PtycError):
         pr["eng"].amp_loss(pr["to"], pr["tp"], [10 ** 6])
     assert pr["eng"].amp_loss(pr["to"], pr["tp"], []) == 0.0
+
+
+def _loss_into(torch, eng, to, tp, idx):
+    """ptyc_amp_loss through the C ABI into gradient buffers filled with NaN
+    beforehand, so an element the library leaves unwritten shows."""
+    import ctypes as C
+
+    from paper_2308_10674_amd import _lib
+    go = torch.full_like(to, complex(float("nan"), float("nan")))
+    gp = torch.full_like(tp, complex(float("nan"), float("nan")))
+    ia = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).ravel())
+    loss = C.c_double()
+    torch.cuda.synchronize()
+    rc = _lib.lib().ptyc_amp_loss(eng._ctx, to.data_ptr(), tp.data_ptr(), ia.ctypes.data_as(C.POINTER(C.c_int64)),
+                                  len(ia), 1.0, go.data_ptr(), gp.data_ptr(), C.byref(loss))
+    assert rc == 0, rc
+    return loss.value, go.cpu().numpy(), gp.cpu().numpy()
+
+
+def test_gradient_edge_minibatches(problem, torch_cuda):
+    """Every element of both gradients is written (the buffers hold NaN
+    before the call): an empty minibatch gives loss 0 and zero gradients;
+    a minibatch that lists one position twice counts its term twice, as
+    the oracle's sum does; minibatches of 1, 16 and 17 positions (one
+    partial sum of dL/dP, exactly one group of 16, one more) and of 120
+    match the FP64 adjoint."""
+    torch = torch_cuda
+    pr = problem
+    wl = pr["wl"]
+    L, go, gp = _loss_into(torch, pr["eng"], pr["to"], pr["tp"], [])
+    assert L == 0.0
+    assert np.all(go == 0) and np.all(gp == 0)
+    base = [int(j) for j in pr["idx"]]
+    cases = {"one": base[:1], "sixteen": base[:16], "seventeen": base[:17], "repeat": base[:9] + base[3:5],
+             "all": base}
+    for name, idx in cases.items():
+        L, go, gp = _loss_into(torch, pr["eng"], pr["to"], pr["tp"], idx)
+        assert np.all(np.isfinite(go)) and np.all(np.isfinite(gp)), name
+        Lo, go_o, gp_o = oracle.amplitude_loss_grad(pr["O"], pr["P"], wl.positions, wl.intensities, np.asarray(idx))
+        mask = oracle.union_mask(wl.positions[np.asarray(idx)], wl.n, wl.h, wl.w)
+        ro, rp = oracle.rel_l2(go, go_o, mask), oracle.rel_l2(gp, gp_o)
+        print(name, len(idx), "loss", abs(L - Lo) / Lo, "grad O", ro, "grad P", rp)
+        assert abs(L - Lo) <= RTOL * Lo, name
+        assert ro <= RTOL and rp <= RTOL, (name, ro, rp)
+        assert np.all(go[~mask] == 0), name
