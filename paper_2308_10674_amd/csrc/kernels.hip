@@ -647,35 +647,40 @@ __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
 }
 
 // Mixed pattern sizes in one launch per stage.  Every size in {64, 128,
-// 256} gets a tile with the same workgroup size (kMixRowNT threads in the
-// row and column stages, kMixInvNT in the inverse stage), so one kernel
+// 256} gets a tile with the same workgroup size (kMixFwdNT threads, one
+// wave, in the forward row stage, kMixRowNT in the column stage, kMixInvNT
+// in the inverse stage), so one kernel
 // serves all of them; a workgroup finds its descriptor and branches (the
 // descriptor is uniform) to the stage of that size.  The tiles change how
 // rows, columns and slots are grouped into workgroups, not the arithmetic
 // of any element, and the partial-maximum layouts do not depend on the
 // tile: the results equal those of the per-size kernels.
-constexpr int kMixRowNT = 256, kMixInvNT = 512;
+constexpr int kMixRowNT = 256, kMixFwdNT = 64, kMixInvNT = 512;
 // The inverse stage has a second tile with fewer slots (S2, R2 rows each)
 // for scans whose batches are small (spiral scans: a handful of positions
 // per batch), so fewer lanes transform idle slots; BatchArgs::itile selects
 // it.
 template <int N> struct MixTile;
-template <> struct MixTile<64>  { static constexpr int RB = 32, R = 4, S = 16, R2 = 8, S2 = 8; };
-template <> struct MixTile<128> { static constexpr int RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
-template <> struct MixTile<256> { static constexpr int RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
+// RF: rows per workgroup of the forward stage (one wave), RB: columns per
+// workgroup of the column stage.
+template <> struct MixTile<64>  { static constexpr int RF = 8, RB = 32, R = 4, S = 16, R2 = 8, S2 = 8; };
+template <> struct MixTile<128> { static constexpr int RF = 4, RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
+template <> struct MixTile<256> { static constexpr int RF = 4, RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
 template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
+template <int N> constexpr int kMixFwdLds = MixTile<N>::RF * Lds<N>::LINE;
 template <int N> constexpr int kMixInvLds = MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE;
 template <int N> constexpr int kMixInvDl = MixTile<N>::S * MixTile<N>::R * N;
 constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 constexpr int kMixRowLdsMax = cmax3(kMixRowLds<64>, kMixRowLds<128>, kMixRowLds<256>);
+constexpr int kMixFwdLdsMax = cmax3(kMixFwdLds<64>, kMixFwdLds<128>, kMixFwdLds<256>);
 constexpr int kMixInvLdsMax = cmax3(kMixInvLds<64>, kMixInvLds<128>, kMixInvLds<256>);
 constexpr int kMixInvDlMax = cmax3(kMixInvDl<64>, kMixInvDl<128>, kMixInvDl<256>);
 
 template <int N>
 __device__ __forceinline__ void mix_rows_fwd(const BatchArgs& a, int local, cf* lds) {
-    using g = RowG<N, MixTile<N>::RB>;
-    static_assert(g::NT == kMixRowNT, "mixed row tile");
-    stage_rows_fwd<N, MixTile<N>::RB>(a, local / g::G, local % g::G, lds);
+    using g = RowG<N, MixTile<N>::RF>;
+    static_assert(g::NT == kMixFwdNT, "mixed row tile");
+    stage_rows_fwd<N, MixTile<N>::RF>(a, local / g::G, local % g::G, lds);
 }
 
 template <int N>
@@ -697,8 +702,8 @@ __device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* 
         stage_rows_inv<N, g::R, g::S>(a, local, lds, dl);
 }
 
-__global__ __launch_bounds__(kMixRowNT) void k_rows_fwd_mix(MultiArgs m) {
-    __shared__ cf lds[kMixRowLdsMax];
+__global__ __launch_bounds__(kMixFwdNT) void k_rows_fwd_mix(MultiArgs m) {
+    __shared__ cf lds[kMixFwdLdsMax];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
@@ -1311,6 +1316,9 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
 }
 
 // ---------------------------------------------------------------- host side
+constexpr int mix_tile_rf(int n) {
+    return n == 64 ? MixTile<64>::RF : n == 128 ? MixTile<128>::RF : n == 256 ? MixTile<256>::RF : 0;
+}
 constexpr int mix_tile_rb(int n) {
     return n == 64 ? MixTile<64>::RB : n == 128 ? MixTile<128>::RB : n == 256 ? MixTile<256>::RB : 0;
 }
@@ -1562,16 +1570,17 @@ bool mixed_n(int n) { return n == 64 || n == 128 || n == 256; }
 
 hipError_t launch_batch_mixed(const BatchArgs* dev_tab, const BatchArgs* host_tab, int count, hipStream_t s) {
     if (count <= 0 || count > kMultiMax) return hipErrorInvalidValue;
-    MultiArgs mr{dev_tab, count, {}}, mi{dev_tab, count, {}};
-    mr.start[0] = mi.start[0] = 0;
+    MultiArgs mf{dev_tab, count, {}}, mr{dev_tab, count, {}}, mi{dev_tab, count, {}};
+    mf.start[0] = mr.start[0] = mi.start[0] = 0;
     for (int i = 0; i < count; ++i) {
         const int n = host_tab[i].n;
         if (!mixed_n(n) || host_tab[i].bsize < 0) return hipErrorInvalidValue;
+        mf.start[i + 1] = mf.start[i] + n / mix_tile_rf(n) * host_tab[i].bsize;
         mr.start[i + 1] = mr.start[i] + n / mix_tile_rb(n) * host_tab[i].bsize;
         mi.start[i + 1] = mi.start[i] + n / mix_tile_r(n, host_tab[i].itile);
     }
     if (mr.start[count] > 0) {
-        hipLaunchKernelGGL(k_rows_fwd_mix, dim3(mr.start[count]), dim3(kMixRowNT), 0, s, mr);
+        hipLaunchKernelGGL(k_rows_fwd_mix, dim3(mf.start[count]), dim3(kMixFwdNT), 0, s, mf);
         hipLaunchKernelGGL(k_cols_mix, dim3(mr.start[count]), dim3(kMixRowNT), 0, s, mr);
     }
     hipLaunchKernelGGL(k_rows_inv_mix, dim3(mi.start[count]), dim3(kMixInvNT), 0, s, mi);

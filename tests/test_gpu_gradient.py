@@ -321,3 +321,21 @@ def test_gradient_edge_minibatches(problem, torch_cuda):
         assert abs(L - Lo) <= RTOL * Lo, name
         assert ro <= RTOL and rp <= RTOL, (name, ro, rp)
         assert np.all(go[~mask] == 0), name
+
+
+def test_gradient_full_size_minibatch(torch_cuda):
+    """The benchmark's gradient workload at its full size: the 3600-position
+    128 px raster on the 1024 x 1024 object, one shuffled minibatch of 512
+    (the benchmark's minibatch), an estimate near the truth; loss and both
+    gradients element-wise against the FP64 adjoint at 1e-5."""
+    from paper_2308_10674_amd import Engine
+    wl = sim.make_config(3)
+    eng = Engine(wl.n, wl.h, wl.w, wl.probe0, wl.object0, mode="coloured", seed=wl.seed)
+    eng.add_positions(wl.positions, wl.intensities)
+    O, P = _near_truth(wl, 77)
+    idx = np.random.default_rng([wl.seed, 9]).permutation(wl.count)[:512]
+    rl, ro, rp, zero_out = _compare(torch_cuda, eng, wl, O, P, idx)
+    print("full-size minibatch: loss", rl, "grad O", ro, "grad P", rp)
+    assert rl <= RTOL and ro <= RTOL and rp <= RTOL, (rl, ro, rp)
+    assert zero_out
+    eng.close()
