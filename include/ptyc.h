@@ -140,7 +140,8 @@ typedef struct ptyc_ingest {
 } ptyc_ingest;
 int ptyc_set_ingest(ptyc_ctx* ctx, const ptyc_ingest* spec);
 
-/* Detector mask in raw frame coordinates (frame_h * frame_w bytes, nonzero
+/* Detector mask (the masking of invalid pixels the paper's Discussion asks
+ * for) in raw frame coordinates (frame_h * frame_w bytes, nonzero
  * = a measured pixel), in mem_kind memory, copied.  At a masked pixel there
  * is no measurement: the modulus replacement keeps the model's value there,
  * the pixel adds nothing to the error metric or to the amplitude loss, and
@@ -148,11 +149,18 @@ int ptyc_set_ingest(ptyc_ctx* ctx, const ptyc_ingest* spec);
 int ptyc_set_mask(ptyc_ctx* ctx, const uint8_t* mask, int mem_kind);
 
 /* Copy the stored amplitudes sqrt(I) of positions first .. first+count-1
- * (count * N * N float32, after preprocessing) to mem_kind memory.
+ * (count * N * N float32, after the preprocessing of section
+ * "Preprocessing"; the export of data the Discussion asks for) to mem_kind
+ * memory.
  * Synchronises.  Errors: PTYC_ERR_ARG for a range outside the loaded data. */
 int ptyc_get_patterns(ptyc_ctx* ctx, int64_t first, int64_t count, float* out, int mem_kind);
 
-/* Run n_sweeps passes (iterations) over the loaded positions.
+/* Run n_sweeps passes (iterations) over the loaded positions: the ePIE
+ * update of section "ePIE Implementation" (the method of Maiden and
+ * Rodenburg 2009 with alpha and beta, a fixed number of iterations, the
+ * position order shuffled anew in every iteration), in strict mode one
+ * position after another, in coloured mode in batches of disjoint windows
+ * whose probe increments are averaged at the end of the batch.
  * order == NULL: the library's schedule; each sweep draws a fresh random
  *   order from (seed, sweep counter) — strict mode: a permutation of all
  *   positions; coloured mode: the colour batches in shuffled order,
@@ -255,7 +263,11 @@ int ptyc_get_schedule(ptyc_ctx* ctx, int64_t* order, int64_t* batch_offsets,
                       int64_t* n_batches);
 
 /* Copy the object (H*W complex64) / probe (N*N complex64) out to, or in
- * from, mem_kind memory.  get_* synchronise the stream. */
+ * from, mem_kind memory: reading out intermediate results while the
+ * reconstruction continues ("Extensions of the ePIE implementation") and
+ * the import and export of object and probe the Discussion asks for
+ * (restart from a saved state).  get_* synchronise the stream.  Errors:
+ * PTYC_ERR_ARG for NULL buffers or an unknown mem_kind. */
 int ptyc_get_object(ptyc_ctx* ctx, void* out, int mem_kind);
 int ptyc_get_probe(ptyc_ctx* ctx, void* out, int mem_kind);
 int ptyc_set_object(ptyc_ctx* ctx, const void* in, int mem_kind);
