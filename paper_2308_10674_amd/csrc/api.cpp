@@ -96,8 +96,10 @@ struct ptyc_ctx {
     DevBuf mbar;                     // arrival counters of the multi-scan persistent kernel (first context of a call)
     int multi_variant = kMultiDefault; // how a multi-context call led by this context launches (kMultiVariants)
     hipGraphExec_t mgexec = nullptr; // multi-scan persistent launch captured as a graph (graph form)
-    const void* mg_tab = nullptr;    // the descriptor table, count and grid the captured graph was built for
+    const void* mg_tab = nullptr;    // the descriptor table, count, grid and barrier counters the captured graph was built for
     int mg_count = 0, mg_grid = 0;
+    const void* mg_bars = nullptr;
+    int mg_nbars = 0;
     DevBuf mask;                     // uint8 [n][n] measured detector pixels (stored layout), if set
     ptyc_ingest ingest{};            // how raw frames become stored amplitudes
     DevBuf staging;                  // host intensities staged on the device
@@ -419,12 +421,15 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
     if ((rc = ensure(c, c->tw, n * sizeof(cf))) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->pmax_part, 2 * (size_t)max_probe_blocks(c) * sizeof(float))) != PTYC_OK) return bail(rc);
     if ((rc = ensure(c, c->bad, sizeof(int))) != PTYC_OK) return bail(rc);
-    if ((rc = ensure(c, c->sync, 2 * sizeof(unsigned))) != PTYC_OK) return bail(rc);
-    if ((e = hipMemsetAsync(c->sync.p, 0, 2 * sizeof(unsigned), c->stream)) != hipSuccess) {
+    c->capacity = persistent_capacity(n);
+    // [0] the persistent sweep's top barrier counter, [1] the barrier fault
+    // flag, then its group counters
+    const size_t sync_bytes = (size_t)bar_words(std::max(c->capacity, 1)) * sizeof(unsigned);
+    if ((rc = ensure(c, c->sync, sync_bytes)) != PTYC_OK) return bail(rc);
+    if ((e = hipMemsetAsync(c->sync.p, 0, sync_bytes, c->stream)) != hipSuccess) {
         hip_fail(c, e, "hipMemsetAsync(sync)");
         return bail(PTYC_ERR_HIP);
     }
-    c->capacity = persistent_capacity(n);
     // twiddles exp(-2 pi i m / n) in double precision, rounded once to float
     std::vector<cf> tw((size_t)n);
     for (int m = 0; m < n; ++m) {
@@ -982,8 +987,9 @@ int share_groups(const std::vector<double>& wt, const std::vector<int>& cap, int
     return sum;
 }
 
-// arrival counters of the multi-scan launch lie kBarStride counters (4 KiB)
-// apart: workgroups of different scans then poll different memory lines
+// the barrier counters of the scans of a multi-scan launch lie a multiple
+// of kBarStride counters (4 KiB) apart: workgroups of different scans then
+// poll different memory lines
 constexpr size_t kBarStride = 1024;
 
 // The persistent multi-scan launch.  Plans are staged (orders and offsets
@@ -1020,11 +1026,15 @@ int multi_persistent(ptyc_ctx* const* ctxs, int n_ctx, int n_sweeps, double* err
     const int grid = share_groups(wt, cap, c0->capacity_multi, g);
     int g0 = 0;
     int rc;
-    if ((rc = ensure(c0, c0->mbar, kMultiMax * kBarStride * sizeof(unsigned))) != PTYC_OK) return rc;
+    size_t stride = kBarStride;   // counters per scan: bar_words of its workgroups, in whole 4 KiB steps
+    for (size_t k = 0; k < sc.size(); ++k)
+        stride = std::max(stride, ((size_t)bar_words(g[k]) + kBarStride - 1) / kBarStride * kBarStride);
+    const int n_bars = (int)(sc.size() * stride);
+    if ((rc = ensure(c0, c0->mbar, (size_t)n_bars * sizeof(unsigned))) != PTYC_OK) return rc;
     for (size_t k = 0; k < sc.size(); ++k) {
         sc[k].g0 = g0;
         sc[k].gn = g[k];
-        sc[k].bar = (unsigned*)c0->mbar.p + k * kBarStride;
+        sc[k].bar = (unsigned*)c0->mbar.p + k * stride;
         g0 += g[k];
     }
     // the descriptor table may still be read by an earlier call's kernels
@@ -1039,14 +1049,14 @@ int multi_persistent(ptyc_ctx* const* ctxs, int n_ctx, int n_sweeps, double* err
         // the launch built as a graph once and replayed while the table, the
         // scan count and the grid stay the same (the table's contents change
         // from call to call; the kernels read them when they run)
-        if (!c0->mgexec || c0->mg_tab != (const void*)dev || c0->mg_count != (int)sc.size() || c0->mg_grid != grid) {
+        if (!c0->mgexec || c0->mg_tab != (const void*)dev || c0->mg_count != (int)sc.size() || c0->mg_grid != grid ||
+            c0->mg_bars != c0->mbar.p || c0->mg_nbars != n_bars) {
             if (c0->mgexec) {
                 HIPCHK(c0, hipGraphExecDestroy(c0->mgexec));
                 c0->mgexec = nullptr;
             }
             hipGraph_t gr = nullptr;
-            HIPCHK(c0, build_multi_graph(dev, (int)sc.size(), grid, (unsigned*)c0->mbar.p,
-                                         (int)(sc.size() * kBarStride), fault, &gr));
+            HIPCHK(c0, build_multi_graph(dev, (int)sc.size(), grid, (unsigned*)c0->mbar.p, n_bars, fault, &gr));
             const hipError_t ie = hipGraphInstantiate(&c0->mgexec, gr, nullptr, nullptr, 0);
             (void)hipGraphDestroy(gr);
             if (ie != hipSuccess) {
@@ -1056,11 +1066,13 @@ int multi_persistent(ptyc_ctx* const* ctxs, int n_ctx, int n_sweeps, double* err
             c0->mg_tab = dev;
             c0->mg_count = (int)sc.size();
             c0->mg_grid = grid;
+            c0->mg_bars = c0->mbar.p;
+            c0->mg_nbars = n_bars;
         }
         HIPCHK(c0, hipGraphLaunch(c0->mgexec, c0->stream));
     } else {
-        HIPCHK(c0, launch_multi_persist(dev, (int)sc.size(), grid, (unsigned*)c0->mbar.p,
-                                        (int)(sc.size() * kBarStride), fault, true, c0->stream));
+        HIPCHK(c0, launch_multi_persist(dev, (int)sc.size(), grid, (unsigned*)c0->mbar.p, n_bars, fault, true,
+                                        c0->stream));
     }
     // each kernel swapped its scan's maxima halves after every non-empty batch
     for (size_t k = 0; k < sc.size(); ++k) {

@@ -69,6 +69,14 @@ struct Shape {
 };
 
 // One scan as a persistent kernel runs it: every batch of n_sweeps sweeps.
+// Software barriers of the persistent kernels: a top counter, then one
+// arrival counter per group of kBarGroup workgroups, each in a line of
+// kBarLine unsigned (128 bytes); bar_words(gn) unsigned hold a barrier of gn
+// workgroups.
+constexpr int kBarGroup = 32, kBarLine = 32;
+constexpr int bar_groups(int gn) { return (gn + kBarGroup - 1) / kBarGroup; }
+constexpr int bar_words(int gn) { return kBarLine * (1 + bar_groups(gn)); }
+
 struct ScanArgs {
     BatchArgs a;              // the scan's buffers; a.order holds the n_sweeps orders, olen entries each;
                               // a.pmax_in / a.pmax_out: the probe maxima halves at the start
@@ -78,7 +86,7 @@ struct ScanArgs {
     int n_sweeps;
     int g0, gn;               // workgroups g0 .. g0 + gn - 1 of the launch serve this scan
     int inv_tile;             // inverse-stage tile of the multi-scan kernel (0 or 1)
-    unsigned* bar;            // arrival counter of those workgroups, zero at the launch
+    unsigned* bar;            // barrier counters of those workgroups (bar_words(gn) unsigned), zero at the launch
     double* err;              // nullptr, or [n_sweeps] running Fourier error of each sweep (multi-scan kernel)
     const double* sum_i;      // [positions] sum of I per position (the error's denominator)
 };
@@ -114,7 +122,8 @@ constexpr int kStrictMaxN = 64;
 hipError_t launch_strict(int n, const BatchArgs& a, int count, hipStream_t s);
 int persistent_capacity(int n);  // co-resident workgroups of the sweep kernel
 // One scan's sweeps as one cooperative launch of at most `capacity`
-// workgroups (the persistent form); the counter sc.bar is zeroed first.
+// workgroups (the persistent form); sc.bar (bar_words(capacity) unsigned,
+// the fault flag at sc.bar[1]) has its counters zeroed first.
 // The kernel swaps the probe maxima halves after every non-empty batch.
 hipError_t launch_sweep(int n, const ScanArgs& sc, int max_batch, int capacity, int* fault, hipStream_t s);
 // Several scans (pattern sizes 64, 128, 256) as one persistent launch of

@@ -931,14 +931,28 @@ __global__ __launch_bounds__(256) void k_fill_zero(cf* p, int64_t n) {
 // the grid always drains.
 constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ inline bool group_barrier(unsigned* bar, unsigned target, int* fault, int* ok_sh) {
+// Arrival is two-level: workgroup `local` of the gn that share the barrier
+// adds one to the counter of its group of kBarGroup consecutive workgroups
+// (bar[kBarLine (g + 1)], a memory line of its own); the group's last
+// arrival adds one to the top counter bar[0], which every workgroup polls
+// until it reaches `target` (the number of group completions so far).  So
+// at most kBarGroup atomics, not gn, queue on any one address.
+__device__ inline bool group_barrier(unsigned* bar, int local, int gn, unsigned target, int* fault, int* ok_sh) {
     // this wave's stores have completed (the coherent ones are written
     // through); the memory clobber keeps the compiler from moving memory
     // accesses across the wait
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int g = local / kBarGroup;
+        const unsigned gsize = (unsigned)min(kBarGroup, gn - g * kBarGroup);
+        // the group counter counts every arrival of every barrier, so the
+        // arrival that completes a multiple of gsize is the group's last
+        // for this barrier (no workgroup passes a barrier before all have
+        // arrived at it)
+        const unsigned v =
+            __hip_atomic_fetch_add(&bar[kBarLine * (g + 1)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((v + 1u) % gsize == 0u) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
         int ok = 1;
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -984,6 +998,7 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
     using ig = InvG<N, IR, IS>;
     BatchArgs a = sc.a;
     unsigned target = 0;
+    const unsigned groups = (unsigned)bar_groups(sc.gn);
     for (int sw = 0; sw < sc.n_sweeps; ++sw) {
         a.order = sc.a.order + (size_t)sw * sc.olen;
         const int64_t* offs = sc.offs + (size_t)sw * (sc.nb + 1);
@@ -995,15 +1010,15 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
             a.bsize = bs;
             for (int it = local; it < bs * rg::G; it += sc.gn)
                 stage_rows_fwd<N, RB, true>(a, it / rg::G, it % rg::G, lds);
-            target += (unsigned)sc.gn;
-            if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
+            target += groups;
+            if (!group_barrier(sc.bar, local, sc.gn, target, fault, ok_sh)) return;
             for (int it = local; it < bs * cg::GC; it += sc.gn)
                 stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds, red);
-            target += (unsigned)sc.gn;
-            if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
+            target += groups;
+            if (!group_barrier(sc.bar, local, sc.gn, target, fault, ok_sh)) return;
             for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, true>(a, it, lds, dl);
-            target += (unsigned)sc.gn;
-            if (!group_barrier(sc.bar, target, fault, ok_sh)) return;
+            target += groups;
+            if (!group_barrier(sc.bar, local, sc.gn, target, fault, ok_sh)) return;
             // the maxima just written are those of the next batch's probe
             float* const next_in = a.pmax_out;
             a.pmax_out = const_cast<float*>(a.pmax_in);
@@ -1254,8 +1269,9 @@ __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count)
     }
 }
 
-__global__ void k_zero_u32(unsigned* p, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+__global__ __launch_bounds__(256) void k_zero_u32(unsigned* p, int n) {
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (i < n) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- ingest
@@ -1510,7 +1526,10 @@ hipError_t sweep_n(const ScanArgs& sc, int max_batch, int capacity, int* fault, 
     constexpr int TB = PTile<N>::B;
     const int need = std::max(max_batch * (N / TB), InvG<N, PTile<N>::R, PTile<N>::S>::GI);
     const int grid = std::min(need, capacity);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, sc.bar, 1);
+    // the top counter (the fault flag beside it stays) and the group counters
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, sc.bar, 1);
+    const int gw = bar_words(grid) - kBarLine;
+    hipLaunchKernelGGL(k_zero_u32, dim3((gw + 255) / 256), dim3(256), 0, s, sc.bar + kBarLine, gw);
     ScanArgs aa = sc;
     aa.g0 = 0;
     aa.gn = grid;
@@ -1673,8 +1692,8 @@ hipError_t build_multi_graph(const ScanArgs* dev_scans, int count, int grid, uns
         void* params[] = {&bars, &n_bars};
         hipKernelNodeParams kp{};
         kp.func = reinterpret_cast<void*>(&k_zero_u32);
-        kp.gridDim = dim3(1);
-        kp.blockDim = dim3(64);
+        kp.gridDim = dim3((unsigned)((n_bars + 255) / 256));
+        kp.blockDim = dim3(256);
         kp.kernelParams = params;
         e = hipGraphAddKernelNode(&zero, g, nullptr, 0, &kp);
     }
@@ -1698,7 +1717,7 @@ hipError_t build_multi_graph(const ScanArgs* dev_scans, int count, int grid, uns
 hipError_t launch_multi_persist(const ScanArgs* dev_scans, int count, int grid, unsigned* bars, int n_bars, int* fault,
                                 bool coop, hipStream_t s) {
     if (count <= 0 || count > kMultiMax || grid <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bars, n_bars);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n_bars + 255) / 256)), dim3(256), 0, s, bars, n_bars);
     if (!coop) {
         hipLaunchKernelGGL(k_multi_persist, dim3(grid), dim3(kMP), 0, s, dev_scans, count, fault);
         return hipGetLastError();
