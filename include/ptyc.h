@@ -286,7 +286,13 @@ int ptyc_set_probe(ptyc_ctx* ctx, const void* in, int mem_kind);
  * replay is preceded by two device-to-device copies of the sweep's order and
  * offsets).  All forms produce the same bytes.  PTYC_FORM_DEFAULT selects
  * PTYC_FORM_BATCH.  Errors: PTYC_ERR_ARG for an unknown form or a
- * persistent grid the device cannot hold. */
+ * persistent grid the device cannot hold.  Every barrier wait of the
+ * persistent kernels (this form and the persistent ptyc_sweep_multi) is
+ * bounded: after PTYC_SPIN_LIMIT polls (environment variable read by
+ * ptyc_init, default 4194304, about 0.1 s) the kernel raises a fault flag and
+ * all its workgroups leave; the next call that synchronises (a sweep with
+ * err_out, get_object, get_probe) then returns PTYC_ERR_HIP and the
+ * context is unusable afterwards. */
 #define PTYC_FORM_DEFAULT 0
 #define PTYC_FORM_BATCH 1
 #define PTYC_FORM_PERSISTENT 2

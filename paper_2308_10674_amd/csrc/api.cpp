@@ -95,6 +95,7 @@ struct ptyc_ctx {
     DevBuf multi;                    // batch descriptors of a multi-context call
     DevBuf mbar;                     // arrival counters of the multi-scan persistent kernel (first context of a call)
     int multi_variant = kMultiDefault; // how a multi-context call led by this context launches (kMultiVariants)
+    unsigned spin_limit = kSpinLimitDefault; // bound of a persistent kernel's barrier wait (PTYC_SPIN_LIMIT at init)
     hipGraphExec_t mgexec = nullptr; // multi-scan persistent launch captured as a graph (graph form)
     const void* mg_tab = nullptr;    // the descriptor table, count, grid and barrier counters the captured graph was built for
     int mg_count = 0, mg_grid = 0;
@@ -155,6 +156,15 @@ int hip_fail(ptyc_ctx* c, hipError_t e, const char* what) {
         hipError_t e_ = (expr);                           \
         if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
     } while (0)
+
+// PTYC_SPIN_LIMIT: polls a software-barrier wait of the persistent kernels
+// may take before it raises the fault flag (default kSpinLimitDefault; a
+// small value forces the failure path in tests)
+unsigned env_spin_limit() {
+    const char* s = std::getenv("PTYC_SPIN_LIMIT");
+    if (!s || !*s) return kSpinLimitDefault;
+    return (unsigned)std::strtoul(s, nullptr, 10);
+}
 
 size_t env_limit() {
     const char* s = std::getenv("PTYC_MAX_DEVICE_BYTES");
@@ -396,6 +406,7 @@ int ptyc_init(ptyc_ctx** out, const ptyc_config* cfg, const void* probe0, const 
         c->col_blocks_max = std::max(c->col_blocks_max, shape_for(cfg->n, kFormBatch, v).col_blocks);
     if (mixed_n(cfg->n)) c->col_blocks_max = std::max(c->col_blocks_max, multi_col_blocks(cfg->n));
     c->dev_limit = env_limit();
+    c->spin_limit = env_spin_limit();
     c->colouring = new Colouring(cfg->n, max_batch_of(c));
     c->ingest.frame_h = c->ingest.frame_w = cfg->n;
     c->ingest.scale = 1.0f;
@@ -1015,6 +1026,7 @@ int multi_persistent(ptyc_ctx* const* ctxs, int n_ctx, int n_sweeps, double* err
         x.inv_tile = n == 64 ? mv.inv64 : n == 128 ? mv.inv128 : 0;
         x.err = err_out ? (double*)c->err_dev.p : nullptr;
         x.sum_i = (const double*)c->sum_i.p;
+        x.spin_limit = c0->spin_limit;
         sc.push_back(x);
         who.push_back(i);
         cap.push_back(multi_need(n, (int)p.max_b, x.inv_tile));
@@ -1146,6 +1158,7 @@ int ptyc_sweep(ptyc_ctx* c, int32_t n_sweeps, const int64_t* order, int64_t orde
             sc.nb = (int)nb;
             sc.n_sweeps = 1;
             sc.bar = (unsigned*)c->sync.p;
+            sc.spin_limit = c->spin_limit;
             sc.sum_i = (const double*)c->sum_i.p;
             size_t e0 = 0;
             if (c->prof) {

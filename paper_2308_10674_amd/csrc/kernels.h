@@ -76,6 +76,8 @@ struct Shape {
 constexpr int kBarGroup = 32, kBarLine = 32;
 constexpr int bar_groups(int gn) { return (gn + kBarGroup - 1) / kBarGroup; }
 constexpr int bar_words(int gn) { return kBarLine * (1 + bar_groups(gn)); }
+// polls of a barrier wait before it gives up (about 0.1 s)
+constexpr unsigned kSpinLimitDefault = 1u << 22;
 
 struct ScanArgs {
     BatchArgs a;              // the scan's buffers; a.order holds the n_sweeps orders, olen entries each;
@@ -88,6 +90,7 @@ struct ScanArgs {
     int inv_tile;             // inverse-stage tile of the multi-scan kernel (0 or 1)
     unsigned* bar;            // barrier counters of those workgroups (bar_words(gn) unsigned), zero at the launch
     double* err;              // nullptr, or [n_sweeps] running Fourier error of each sweep (multi-scan kernel)
+    unsigned spin_limit;      // polls a barrier wait may take before it raises the fault flag
     const double* sum_i;      // [positions] sum of I per position (the error's denominator)
 };
 

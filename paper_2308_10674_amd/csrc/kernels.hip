@@ -927,9 +927,8 @@ __global__ __launch_bounds__(256) void k_fill_zero(cf* p, int64_t n) {
 // polls until every workgroup of the scan has arrived.  All data the stages
 // pass between workgroups goes through the coherent accesses (COH = true),
 // so no cache write-back or invalidation is needed.  Every wait is bounded;
-// on expiry the fault flag is raised and the waiting workgroups leave, so
-// the grid always drains.
-constexpr unsigned kSpinLimit = 1u << 22;
+// on expiry (ScanArgs::spin_limit polls) the fault flag is raised and the
+// waiting workgroups leave, so the grid always drains.
 
 // Arrival is two-level: workgroup `local` of the gn that share the barrier
 // adds one to the counter of its group of kBarGroup consecutive workgroups
@@ -937,7 +936,8 @@ constexpr unsigned kSpinLimit = 1u << 22;
 // arrival adds one to the top counter bar[0], which every workgroup polls
 // until it reaches `target` (the number of group completions so far).  So
 // at most kBarGroup atomics, not gn, queue on any one address.
-__device__ inline bool group_barrier(unsigned* bar, int local, int gn, unsigned target, int* fault, int* ok_sh) {
+__device__ inline bool group_barrier(unsigned* bar, int local, int gn, unsigned target, unsigned spin_limit,
+                                     int* fault, int* ok_sh) {
     // this wave's stores have completed (the coherent ones are written
     // through); the memory clobber keeps the compiler from moving memory
     // accesses across the wait
@@ -957,8 +957,9 @@ __device__ inline bool group_barrier(unsigned* bar, int local, int gn, unsigned 
         int ok = 1;
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if ((++spins & 1023u) == 0u &&
-                (spins > kSpinLimit || __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            // the bound on every poll, another workgroup's fault every 1024
+            if (++spins >= spin_limit ||
+                ((spins & 1023u) == 0u && __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                 __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
@@ -1011,14 +1012,14 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
             for (int it = local; it < bs * rg::G; it += sc.gn)
                 stage_rows_fwd<N, RB, true>(a, it / rg::G, it % rg::G, lds);
             target += groups;
-            if (!group_barrier(sc.bar, local, sc.gn, target, fault, ok_sh)) return;
+            if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
             for (int it = local; it < bs * cg::GC; it += sc.gn)
                 stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds, red);
             target += groups;
-            if (!group_barrier(sc.bar, local, sc.gn, target, fault, ok_sh)) return;
+            if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
             for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, true>(a, it, lds, dl);
             target += groups;
-            if (!group_barrier(sc.bar, local, sc.gn, target, fault, ok_sh)) return;
+            if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
             // the maxima just written are those of the next batch's probe
             float* const next_in = a.pmax_out;
             a.pmax_out = const_cast<float*>(a.pmax_in);

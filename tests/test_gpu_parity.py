@@ -470,3 +470,31 @@ def test_device_memory_cap_gives_oom(monkeypatch):
         eng.add_positions(wl.positions, wl.intensities)         # the stack does not
     assert e.value.status == L.PTYC_ERR_OOM
     assert eng.num_positions == 0
+
+
+def test_barrier_timeout_is_reported(monkeypatch):
+    """The bounded barrier waits of the persistent kernels, forced from the
+    host (PTYC_SPIN_LIMIT=1: a workgroup that has to wait at a barrier gives
+    up after one poll): the kernel raises its fault flag and drains, the
+    sweep reports PTYC_ERR_HIP and the context refuses further work; a
+    context created without the setting is unaffected."""
+    from paper_2308_10674_amd import Engine, PtycError, _lib as L, sweep_multi
+    wl = sim.make_config(1, n_positions=300)
+    monkeypatch.setenv("PTYC_SPIN_LIMIT", "1")
+    eng = engine_for(wl, form="persistent")
+    with pytest.raises(PtycError) as e:
+        eng.sweep(1, errors=True)
+    assert e.value.status == L.PTYC_ERR_HIP
+    with pytest.raises(PtycError) as e:
+        eng.get_object()
+    assert e.value.status == L.PTYC_ERR_STATE
+    # the several-scan persistent kernel (variant 0)
+    pair = [engine_for(sim.make_config(1, n_positions=120)) for _ in range(2)]
+    pair[0].multi_variant = 0
+    with pytest.raises(PtycError) as e:
+        sweep_multi(pair, 1, errors=True)
+    assert e.value.status == L.PTYC_ERR_HIP
+    monkeypatch.delenv("PTYC_SPIN_LIMIT")
+    ok = engine_for(wl, form="persistent")
+    ok.sweep(1, errors=True)
+    assert np.all(np.isfinite(ok.get_object()))
