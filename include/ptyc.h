@@ -378,7 +378,7 @@ const char* ptyc_init_error(void);
  * minibatch size (about N^2 complex64 per position).  Synchronises the
  * stream.  Errors:
  * PTYC_ERR_ARG for NULL buffers, an index that is not loaded, only one
- * gradient buffer, a non-finite scale. */
+ * gradient buffer, a non-finite scale, more than 2^24 positions. */
 int ptyc_amp_loss(ptyc_ctx* ctx, const void* obj, const void* probe, const int64_t* idx,
                   int64_t count, float grad_scale, void* grad_obj, void* grad_probe,
                   double* loss_out);

@@ -1555,6 +1555,8 @@ int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int6
     if ((grad_obj == nullptr) != (grad_probe == nullptr))
         return fail(c, PTYC_ERR_ARG, "grad_obj and grad_probe must both be given or both be NULL");
     if (count < 0 || (count > 0 && !idx)) return fail(c, PTYC_ERR_ARG, "bad index list");
+    // slot and tile-list indices are 32-bit on the device
+    if (count > (int64_t)1 << 24) return fail(c, PTYC_ERR_ARG, "minibatch larger than 2^24 positions");
     if (!std::isfinite(grad_scale)) return fail(c, PTYC_ERR_ARG, "grad_scale must be finite");
     for (int64_t i = 0; i < count; ++i)
         if (idx[i] < 0 || idx[i] >= c->n_loaded)
