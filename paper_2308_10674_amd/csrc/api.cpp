@@ -114,6 +114,18 @@ struct ptyc_ctx {
     size_t pinned_bytes = 0;
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
+    // pinned upload buffers of the amplitude loss, used in turn: the host
+    // prepares a minibatch while the uploads of the previous ones are still
+    // queued (it waits only for the upload made kLossRing calls earlier)
+    struct PinSlot {
+        void* p = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    static constexpr int kLossRing = 4;
+    PinSlot lpin[kLossRing];
+    int lring = 0;
 
     size_t dev_bytes = 0, dev_limit = 0;
 
@@ -471,6 +483,10 @@ void ptyc_destroy(ptyc_ctx* c) {
     for (DevBuf* b : bufs) release(*b);
     if (c->pinned_order) (void)hipHostFree(c->pinned_order);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    for (auto& ps : c->lpin) {
+        if (ps.p) (void)hipHostFree(ps.p);
+        if (ps.done) (void)hipEventDestroy(ps.done);
+    }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c->colouring;
     delete c;
@@ -1609,34 +1625,37 @@ int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int6
     const size_t obytes = (size_t)count * sizeof(OrderEntry);
     const size_t tbytes = (tile_off.size() + tile_slot.size()) * sizeof(int32_t);
     const size_t ubytes = obytes + tbytes;
-    // the pinned upload buffer may still feed an earlier copy
-    if (c->upload_pending) {
-        HIPCHK(c, hipEventSynchronize(c->upload_done));
-        c->upload_pending = false;
-    }
     if ((rc = ensure(c, c->order, std::max<size_t>(ubytes, sizeof(OrderEntry)))) != PTYC_OK) return rc;
     if ((rc = ensure(c, c->err_part, (size_t)slots * c->sb.col_blocks * sizeof(double))) != PTYC_OK) return rc;
-    if (c->pinned_bytes < ubytes) {
-        if (c->pinned_order) (void)hipHostFree(c->pinned_order);
-        c->pinned_order = nullptr;
-        c->pinned_bytes = 0;
-        hipError_t e = hipHostMalloc((void**)&c->pinned_order, ubytes, hipHostMallocDefault);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, PTYC_ERR_OOM, "pinned host allocation failed");
-        }
-        c->pinned_bytes = ubytes;
-    }
     const int32_t* d_tile_off = (const int32_t*)((const char*)c->order.p + obytes);
     const int32_t* d_tile_slot = d_tile_off + tile_off.size();
     if (ubytes > 0) {
-        to_entries(c, idx, count, (OrderEntry*)c->pinned_order);
-        int32_t* pt = (int32_t*)((char*)c->pinned_order + obytes);
+        // this call's pinned buffer may still feed the copy made kLossRing calls ago
+        ptyc_ctx::PinSlot& ps = c->lpin[c->lring];
+        c->lring = (c->lring + 1) % ptyc_ctx::kLossRing;
+        if (ps.pending) {
+            HIPCHK(c, hipEventSynchronize(ps.done));
+            ps.pending = false;
+        }
+        if (!ps.done) HIPCHK(c, hipEventCreateWithFlags(&ps.done, hipEventDisableTiming));
+        if (ps.bytes < ubytes) {
+            if (ps.p) (void)hipHostFree(ps.p);
+            ps.p = nullptr;
+            ps.bytes = 0;
+            hipError_t e = hipHostMalloc(&ps.p, ubytes, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, PTYC_ERR_OOM, "pinned host allocation failed");
+            }
+            ps.bytes = ubytes;
+        }
+        to_entries(c, idx, count, (OrderEntry*)ps.p);
+        int32_t* pt = (int32_t*)((char*)ps.p + obytes);
         std::copy(tile_off.begin(), tile_off.end(), pt);
         std::copy(tile_slot.begin(), tile_slot.end(), pt + tile_off.size());
-        HIPCHK(c, hipMemcpyAsync(c->order.p, c->pinned_order, ubytes, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
-        c->upload_pending = true;
+        HIPCHK(c, hipMemcpyAsync(c->order.p, ps.p, ubytes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipEventRecord(ps.done, c->stream));
+        ps.pending = true;
     }
     BatchArgs a = base_args(c);
     a.obj = (cf*)obj;

@@ -1325,8 +1325,17 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
                                                     const double* sum_i, double* out, int raw) {
     __shared__ double red[256 / kWave];
     double num = 0.0, den = 0.0;
-    for (int64_t i = threadIdx.x; i < n_part; i += 256) num += err_part[i];
-    for (int64_t i = threadIdx.x; i < order_len; i += 256) den += sum_i[order[i].j];
+    // each thread's strided sum in index order, eight loads in flight
+    int64_t i = threadIdx.x;
+    for (; i + 7 * 256 < n_part; i += 8 * 256) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = err_part[i + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) num += t[u];
+    }
+    for (; i < n_part; i += 256) num += err_part[i];
+    for (int64_t k = threadIdx.x; k < order_len; k += 256) den += sum_i[order[k].j];
     num = block_sum<256>(num, red);
     den = block_sum<256>(den, red);
     if (threadIdx.x == 0) *out = raw ? num : (den > 0.0 ? num / den : 0.0);
