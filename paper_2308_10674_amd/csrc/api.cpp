@@ -1664,15 +1664,29 @@ int amp_loss_enqueue(ptyc_ctx* c, const void* obj, const void* probe, const int6
     a.off = 0;
     a.bsize = (int)count;
     HIPCHK(c, launch_loss_fwd(n, a, grad, c->stream));
-    if (grad) {
-        if (count > 0) {
-            HIPCHK(c, launch_adjoint_rows(n, a, c->gpart.p, c->stream));
-            HIPCHK(c, launch_probe_grad_sum(c->gpart.p, (int64_t)nn, (int)parts, grad_probe, c->stream));
-        }
-        HIPCHK(c, launch_obj_grad_gather(c->scratch.p, (const OrderEntry*)c->order.p, n, h, w, d_tile_off, d_tile_slot,
-                                         grad_obj, c->stream));
+    if (!grad) {
+        HIPCHK(c, launch_sum_reduce((const double*)c->err_part.p, count * c->sb.col_blocks, loss_dev, c->stream));
+        return PTYC_OK;
     }
-    HIPCHK(c, launch_sum_reduce((const double*)c->err_part.p, count * c->sb.col_blocks, loss_dev, c->stream));
+    if (count > 0) HIPCHK(c, launch_adjoint_rows(n, a, c->gpart.p, c->stream));
+    // dL/dO, dL/dP and the loss sum in one launch
+    GradFinish f{};
+    f.co = (const cf*)c->scratch.p;
+    f.order = (const OrderEntry*)c->order.p;
+    f.n = n;
+    f.h = h;
+    f.w = w;
+    f.tile_off = d_tile_off;
+    f.tile_slot = d_tile_slot;
+    f.gobj = (cf*)grad_obj;
+    f.part = (const cf*)c->gpart.p;
+    f.nn = count > 0 ? (int64_t)nn : 0;   // an empty minibatch: dL/dP was cleared above
+    f.parts = (int)parts;
+    f.gprobe = (cf*)grad_probe;
+    f.loss_part = (const double*)c->err_part.p;
+    f.n_loss_part = count * c->sb.col_blocks;
+    f.loss = loss_dev;
+    HIPCHK(c, launch_grad_finish(f, c->stream));
     return PTYC_OK;
 }
 

@@ -169,16 +169,35 @@ hipError_t launch_loss_fwd(int n, const BatchArgs& a, bool grad, hipStream_t s);
 // groups = ceil(bsize / kAdjGroup)).
 constexpr int kAdjGroup = 16, kAdjLanes = 4;
 hipError_t launch_adjoint_rows(int n, const BatchArgs& a, void* part, hipStream_t s);
-// dL/dP = the `parts` partial sums (nn complex64 each) added in order, into gprobe
-hipError_t launch_probe_grad_sum(const void* part, int64_t nn, int parts, void* gprobe, hipStream_t s);
+// The last launch of a loss with gradient.  dL/dP = the `parts` partial
+// sums of dL/dP (nn complex64 each, at part) added in order, into gprobe;
 // dL/dO over the whole h x w object by tiles of kGradTR x kGradTC pixels
-// (row-major tile index t, ceil(w / kGradTC) tiles per row): tile t sums
-// the contributions co_slot of the slots tile_slot[tile_off[t] ..
-// tile_off[t + 1]) (ascending) over the pixels each window covers and
-// writes every pixel of the tile to gobj
+// (row-major tile index t, ceil(w / kGradTC) tiles per row): tile t sums the
+// contributions co of the slots tile_slot[tile_off[t] .. tile_off[t + 1])
+// (ascending; slot k's contribution is n x n at co + k n^2 over the window
+// at order[k]) and writes every pixel of the tile to gobj; the loss = the
+// n_loss_part partials at loss_part summed as launch_sum_reduce does, into
+// the device double *loss.  tiles_x, n_tiles and probe_blocks are filled in
+// by the launcher.
 constexpr int kGradTR = 16, kGradTC = 64;
-hipError_t launch_obj_grad_gather(const void* co_slot, const OrderEntry* order, int n, int64_t h, int64_t w,
-                                  const int* tile_off, const int* tile_slot, void* gobj, hipStream_t s);
+struct GradFinish {
+    const cf* co;
+    const OrderEntry* order;
+    int n;
+    int64_t h, w;
+    const int* tile_off;
+    const int* tile_slot;
+    cf* gobj;
+    const cf* part;
+    int64_t nn;
+    int parts;
+    cf* gprobe;
+    const double* loss_part;
+    int64_t n_loss_part;
+    double* loss;
+    int tiles_x, n_tiles, probe_blocks;
+};
+hipError_t launch_grad_finish(GradFinish f, hipStream_t s);
 // multiply count complex values in place by the device scalar *scale
 hipError_t launch_scale(void* p, int64_t count_c64, const double* scale, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t count_c64, hipStream_t s);

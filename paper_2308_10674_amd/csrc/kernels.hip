@@ -849,9 +849,9 @@ __global__ __launch_bounds__(kAdjLanes * kWave) void k_rows_adj(BatchArgs a, cf*
 }
 
 // dL/dP: the groups' partial sums added in group order, eight loads in
-// flight at a time
-__global__ __launch_bounds__(256) void k_probe_grad_sum(const cf* part, int64_t nn, int parts, cf* gprobe) {
-    const int64_t el = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// flight at a time (block blk of 256 elements)
+__device__ inline void probe_grad_sum(const cf* part, int64_t nn, int parts, cf* gprobe, int blk) {
+    const int64_t el = (int64_t)blk * 256 + threadIdx.x;
     if (el >= nn) return;
     cf acc = cf{0.f, 0.f};
     int q = 0;
@@ -867,14 +867,12 @@ __global__ __launch_bounds__(256) void k_probe_grad_sum(const cf* part, int64_t 
 }
 
 // dL/dO by object tiles of kGradTR x kGradTC pixels, one workgroup per
-// tile: each pixel of the tile gets the sum of the contributions of the
-// windows that cover it, over the slots listed for the tile (ascending), and
-// every pixel is written (zero where no window reaches).
-__global__ __launch_bounds__(256) void k_obj_grad_gather(const cf* co_slot, const OrderEntry* order, int n,
-                                                        int64_t h, int64_t w, int tiles_x, const int* tile_off,
-                                                        const int* tile_slot, cf* gobj) {
+// tile (tile tid): each pixel of the tile gets the sum of the contributions
+// of the windows that cover it, over the slots listed for the tile
+// (ascending), and every pixel is written (zero where no window reaches).
+__device__ inline void obj_grad_gather(const cf* co_slot, const OrderEntry* order, int n, int64_t h, int64_t w,
+                                       int tiles_x, const int* tile_off, const int* tile_slot, cf* gobj, int tid) {
     constexpr int kRowsPerPass = 256 / kGradTC, KR = kGradTR / kRowsPerPass, U = 8;
-    const int tid = (int)blockIdx.x;
     const int64_t y0 = (int64_t)(tid / tiles_x) * kGradTR, x0 = (int64_t)(tid % tiles_x) * kGradTC;
     const int cx = (int)threadIdx.x % kGradTC, ry = (int)threadIdx.x / kGradTC;
     const int64_t x = x0 + cx;
@@ -1320,10 +1318,8 @@ __global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ src, f
 }
 
 // ---------------------------------------------------------------- error
-__global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int64_t n_part,
-                                                    const OrderEntry* order, int64_t order_len,
-                                                    const double* sum_i, double* out, int raw) {
-    __shared__ double red[256 / kWave];
+__device__ inline void err_reduce(const double* err_part, int64_t n_part, const OrderEntry* order, int64_t order_len,
+                                  const double* sum_i, double* out, int raw, double* red) {
     double num = 0.0, den = 0.0;
     // each thread's strided sum in index order, eight loads in flight
     int64_t i = threadIdx.x;
@@ -1339,6 +1335,28 @@ __global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int6
     num = block_sum<256>(num, red);
     den = block_sum<256>(den, red);
     if (threadIdx.x == 0) *out = raw ? num : (den > 0.0 ? num / den : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_err_reduce(const double* err_part, int64_t n_part,
+                                                    const OrderEntry* order, int64_t order_len,
+                                                    const double* sum_i, double* out, int raw) {
+    __shared__ double red[256 / kWave];
+    err_reduce(err_part, n_part, order, order_len, sum_i, out, raw, red);
+}
+
+// The last launch of a loss with gradient, three independent parts by
+// workgroup range: the dL/dO tiles, then the dL/dP element blocks, then one
+// workgroup summing the loss partials.
+__global__ __launch_bounds__(256) void k_grad_finish(GradFinish f) {
+    __shared__ double red[256 / kWave];
+    const int b = (int)blockIdx.x;
+    if (b < f.n_tiles) {
+        obj_grad_gather(f.co, f.order, f.n, f.h, f.w, f.tiles_x, f.tile_off, f.tile_slot, f.gobj, b);
+    } else if (b < f.n_tiles + f.probe_blocks) {
+        probe_grad_sum(f.part, f.nn, f.parts, f.gprobe, b - f.n_tiles);
+    } else {
+        err_reduce(f.loss_part, f.n_loss_part, nullptr, 0, nullptr, f.loss, 1, red);
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -1753,20 +1771,13 @@ hipError_t launch_adjoint_rows(int n, const BatchArgs& a, void* part, hipStream_
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_probe_grad_sum(const void* part, int64_t nn, int parts, void* gprobe, hipStream_t s) {
-    hipLaunchKernelGGL(k_probe_grad_sum, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, (const cf*)part, nn,
-                       parts, (cf*)gprobe);
+hipError_t launch_grad_finish(GradFinish f, hipStream_t s) {
+    f.tiles_x = (int)((f.w + kGradTC - 1) / kGradTC);
+    f.n_tiles = f.tiles_x * (int)((f.h + kGradTR - 1) / kGradTR);
+    f.probe_blocks = (int)((f.nn + 255) / 256);
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)(f.n_tiles + f.probe_blocks + 1)), dim3(256), 0, s, f);
     return hipGetLastError();
 }
-
-hipError_t launch_obj_grad_gather(const void* co_slot, const OrderEntry* order, int n, int64_t h, int64_t w,
-                                  const int* tile_off, const int* tile_slot, void* gobj, hipStream_t s) {
-    const int tiles_x = (int)((w + kGradTC - 1) / kGradTC), tiles_y = (int)((h + kGradTR - 1) / kGradTR);
-    hipLaunchKernelGGL(k_obj_grad_gather, dim3((unsigned)(tiles_x * tiles_y)), dim3(256), 0, s, (const cf*)co_slot,
-                       order, n, h, w, tiles_x, tile_off, tile_slot, (cf*)gobj);
-    return hipGetLastError();
-}
-
 hipError_t launch_scale(void* p, int64_t count_c64, const double* scale, hipStream_t s) {
     if (count_c64 <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((count_c64 + 255) / 256, 4096);
