@@ -22,18 +22,18 @@ class AmplitudeLoss(torch.autograd.Function):
         # loss and, when an input needs it, both gradients in one pass of
         # the kernels; nothing here waits for the GPU
         grad = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
-        loss, g_obj, g_probe = engine.amp_loss_async(obj, probe, idx, grad=grad)
+        loss, flat, g_obj, g_probe = engine._amp_loss_flat(obj, probe, idx, grad)
         ctx.engine = engine
-        ctx.grads = (g_obj, g_probe)
+        ctx.grads = (flat, g_obj, g_probe)
         return loss
 
     @staticmethod
     def backward(ctx, grad_out):
-        g_obj, g_probe = ctx.grads
+        flat, g_obj, g_probe = ctx.grads
         ctx.grads = None
-        # the upstream gradient scales the saved gradients (library kernel)
-        ctx.engine.scale_(g_obj, grad_out)
-        ctx.engine.scale_(g_probe, grad_out)
+        # the upstream gradient scales the saved gradients, both in one
+        # library call (they share one buffer)
+        ctx.engine.scale_(flat, grad_out)
         return g_obj, g_probe, None, None
 
 

@@ -218,8 +218,15 @@ class Engine:
 
     def amp_loss_async(self, obj, probe, idx, grad=True):
         """Loss (a float64 CUDA scalar tensor) and, with ``grad``, dL/dO and
-        dL/dP as new device tensors, all filled in when the enqueued work
-        runs on the stream (nothing waits for it here)."""
+        dL/dP as device tensors, all filled in when the enqueued work runs
+        on the stream (nothing waits for it here).  The two gradients are
+        views of one allocation (dL/dO, then dL/dP)."""
+        loss, flat, go, gp = self._amp_loss_flat(obj, probe, idx, grad)
+        return loss, go, gp
+
+    def _amp_loss_flat(self, obj, probe, idx, grad):
+        """amp_loss_async, also returning the one buffer that holds both
+        gradients (so one scaling call covers them)."""
         o = obj.detach()
         p = probe.detach()
         if not (o.is_cuda and p.is_cuda) or o.dtype != torch.complex64 or p.dtype != torch.complex64:
@@ -228,14 +235,17 @@ class Engine:
         p = p.contiguous()
         ia, ip = _i64(np.asarray(idx, dtype=np.int64).ravel())
         loss = torch.empty((), dtype=torch.float64, device=o.device)
-        go = torch.empty_like(o) if grad else None
-        gp = torch.empty_like(p) if grad else None
+        flat = go = gp = None
+        if grad:
+            flat = torch.empty(o.numel() + p.numel(), dtype=torch.complex64, device=o.device)
+            go = flat[:o.numel()].view(o.shape)
+            gp = flat[o.numel():].view(p.shape)
         _check(L.lib().ptyc_amp_loss_async(self._ctx, o.data_ptr(), p.data_ptr(), ip, len(ia),
                                            go.data_ptr() if grad else None, gp.data_ptr() if grad else None,
                                            loss.data_ptr()), self._ctx)
         # the inputs and outputs must outlive the enqueued work: torch's
         # caching allocator reuses freed blocks only in stream order
-        return loss, go, gp
+        return loss, flat, go, gp
 
     def scale_(self, data, scale_dev):
         """data (complex64 CUDA tensor) *= scale_dev (float64 CUDA scalar),
