@@ -149,9 +149,10 @@ int ptyc_set_ingest(ptyc_ctx* ctx, const ptyc_ingest* spec);
 int ptyc_set_mask(ptyc_ctx* ctx, const uint8_t* mask, int mem_kind);
 
 /* Copy the stored amplitudes sqrt(I) of positions first .. first+count-1
- * (count * N * N float32, after the preprocessing of section
+ * (count * N * N float32, row-major, after the preprocessing of section
  * "Preprocessing"; the export of data the Discussion asks for) to mem_kind
- * memory.
+ * memory (the library keeps them in blocks of 16 columns and reorders them
+ * on the way out).
  * Synchronises.  Errors: PTYC_ERR_ARG for a range outside the loaded data. */
 int ptyc_get_patterns(ptyc_ctx* ctx, int64_t first, int64_t count, float* out, int mem_kind);
 

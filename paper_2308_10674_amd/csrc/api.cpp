@@ -759,8 +759,24 @@ int ptyc_get_patterns(ptyc_ctx* c, int64_t first, int64_t count, float* out, int
     if (count == 0) return PTYC_OK;
     if (!out || !valid_kind(kind)) return fail(c, PTYC_ERR_ARG, "bad output buffer or mem_kind");
     const size_t nn = (size_t)c->cfg.n * c->cfg.n;
-    HIPCHK(c, hipMemcpyAsync(out, (const float*)c->sqrt_i.p + (size_t)first * nn, (size_t)count * nn * sizeof(float),
-                             from_dev(kind), c->stream));
+    const float* src = (const float*)c->sqrt_i.p + (size_t)first * nn;
+    // the stored layout (column blocks) back to row-major order: directly
+    // into a device destination, through the staging buffer for the host
+    if (kind == PTYC_MEM_DEVICE) {
+        HIPCHK(c, launch_amp_rowmajor(c->cfg.n, src, out, count, c->stream));
+    } else {
+        const int64_t chunk = std::max<int64_t>(1, (int64_t)((size_t)(64u << 20) / (nn * sizeof(float))));
+        const int64_t cn = std::min(chunk, count);
+        int rc2;
+        if ((rc2 = ensure(c, c->staging, (size_t)cn * nn * sizeof(float))) != PTYC_OK) return rc2;
+        for (int64_t k = 0; k < count; k += cn) {
+            const int64_t m = std::min(cn, count - k);
+            HIPCHK(c, launch_amp_rowmajor(c->cfg.n, src + (size_t)k * nn, (float*)c->staging.p, m, c->stream));
+            HIPCHK(c, hipMemcpyAsync(out + (size_t)k * nn, c->staging.p, (size_t)m * nn * sizeof(float),
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PTYC_OK;
 }

@@ -15,13 +15,24 @@ struct OrderEntry {
     int64_t j;                // position index (row of sqrt_i, sum_i)
 };
 
+// Stored amplitudes sqrt(I) of one position: N x N floats in blocks of
+// kAmpBlock columns, block after block; element (row r, column c) at
+// amp_at(N, r, c).  A column workgroup of kAmpBlock columns (or a multiple)
+// then reads whole 64-byte row segments lying back to back, instead of
+// sharing 128-byte lines with the workgroup of the neighbouring columns.
+// At N = 16 this is the row-major layout.
+constexpr int kAmpBlock = 16;
+__host__ __device__ constexpr int amp_at(int n, int r, int c) {
+    return ((c / kAmpBlock) * n + r) * kAmpBlock + c % kAmpBlock;
+}
+
 // Everything one batch of positions needs.  Device pointers only.
 struct BatchArgs {
     cf* obj;                  // [h][w] object, updated in place
     int64_t h, w;
     cf* probe;                // [n][n] probe P_b (read by the stages, written by the reduce)
     const cf* tw;             // [n] exp(-2 pi i m / n)
-    const float* sqrt_i;      // [cap][n][n] measured moduli
+    const float* sqrt_i;      // [cap][n x n] measured moduli, each position in the amp_at layout
     const int2* pos;          // [cap] window corners (row, col)
     const OrderEntry* order;  // this sweep's order
     int64_t off;              // first order entry of this batch
@@ -206,6 +217,9 @@ hipError_t launch_mean(void* const* ptrs, int k, int64_t count_c64, hipStream_t 
 hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hipStream_t s);
 hipError_t launch_ingest(int n, const float* src, float* sqrt_i_dst, double* sum_i_dst,
                          int64_t count, const IngestSpec& spec, int* bad_flag, hipStream_t s);
+// count positions' stored amplitudes (amp_at layout) to row-major n x n
+// arrays at dst (device memory)
+hipError_t launch_amp_rowmajor(int n, const float* src, float* dst, int64_t count, hipStream_t s);
 hipError_t launch_err_reduce(const double* err_part, int64_t n_part, const OrderEntry* order,
                              int64_t order_len, const double* sum_i, double* err_out,
                              hipStream_t s);

@@ -358,7 +358,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
     const int64_t j = a.order[a.off + slot].j;
     const int c = cb * CB + cl;
     cf* base = a.scratch + (size_t)slot * N * N + c;
-    const float* ampb = a.sqrt_i + (size_t)j * N * N + c;
+    const float* ampb = a.sqrt_i + (size_t)j * N * N + amp_at(N, 0, c);   // row r at ampb[r * kAmpBlock]
     cf v[g::N1];
     float amp[g::N1];
 #pragma unroll
@@ -367,7 +367,7 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 #pragma unroll
     for (int i = 0; i < g::N1; ++i) {
         const int row = Fact<N>::out(t, i);
-        amp[i] = ampb[(size_t)row * N];
+        amp[i] = ampb[(size_t)row * kAmpBlock];
         valid[i] = a.mask == nullptr || a.mask[row * N + c] != 0;
     }
     twiddles_binv<N, +1>(wb, t, a.tw);
@@ -1163,9 +1163,9 @@ __global__ __launch_bounds__(kStrictNT<N>) void k_strict(BatchArgs a, int count)
     constexpr float inv = 1.0f / (float)(N * N);
     // sqrt(I) of column l of a position, in the order the column pass holds it
     auto load_amp = [&](int64_t j, float* amp) {
-        const float* ampb = a.sqrt_i + (size_t)j * N * N + l;
+        const float* ampb = a.sqrt_i + (size_t)j * N * N + amp_at(N, 0, l);
 #pragma unroll
-        for (int i = 0; i < N1; ++i) amp[i] = ampb[(size_t)F::out(t, i) * N];
+        for (int i = 0; i < N1; ++i) amp[i] = ampb[(size_t)F::out(t, i) * kAmpBlock];
     };
     float amp[N1];
     OrderEntry e = a.order[a.off];
@@ -1310,11 +1310,19 @@ __global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ src, f
                 acc += (double)v;
             }
         }
-        d[a * N + b] = amp;
+        d[amp_at(N, a, b)] = amp;
     }
     if (badl) atomicOr(bad, 1);
     const double tot = block_sum<256>(acc, red);
     if (threadIdx.x == 0) sum_i[i] = tot;
+}
+
+// stored amplitudes of position blockIdx.x back to row-major order
+template <int N>
+__global__ __launch_bounds__(256) void k_amp_rowmajor(const float* __restrict__ src, float* dst) {
+    const float* a = src + (size_t)blockIdx.x * N * N;
+    float* d = dst + (size_t)blockIdx.x * N * N;
+    for (int e = threadIdx.x; e < N * N; e += 256) d[e] = a[amp_at(N, e / N, e % N)];
 }
 
 // ---------------------------------------------------------------- error
@@ -1796,6 +1804,18 @@ hipError_t launch_sum_reduce(const double* part, int64_t n_part, double* out, hi
     hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, s, part, n_part, (const OrderEntry*)nullptr,
                        (int64_t)0, (const double*)nullptr, out, 1);
     return hipGetLastError();
+}
+
+template <int N>
+hipError_t amp_rowmajor_n(const float* src, float* dst, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_amp_rowmajor<N>, dim3((unsigned)count), dim3(256), 0, s, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_amp_rowmajor(int n, const float* src, float* dst, int64_t count, hipStream_t s) {
+    PTYC_DISPATCH(n, amp_rowmajor_n<N>(src, dst, count, s));
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ingest(int n, const float* src, float* dst, double* sum_i, int64_t count,
