@@ -120,6 +120,46 @@ def test_every_multi_variant_equals_individual_sweeps(variant):
         np.testing.assert_allclose(err_m[k], err_a, rtol=1e-13)
 
 
+def _spiral_scans():
+    """Fermat spirals whose colour batches hold 1-9 positions (64, 128 and
+    256 px), so the eight-slot inverse tile of the stepped launches runs
+    with one and with two slot rounds."""
+    out = []
+    for k, (n, rfac, count) in enumerate([(64, 4.0, 300), (128, 12.0, 250), (256, 24.0, 300)]):
+        t = np.arange(count, dtype=np.float64)
+        rho = rfac * np.sqrt(t)
+        th = t * np.pi * (3.0 - np.sqrt(5.0))
+        cen = np.stack([np.rint(rho * np.sin(th)), np.rint(rho * np.cos(th))], 1)
+        h, w, corners = sim.object_extent(cen, n, 32)
+        r = {64: 20.0, 128: 40.0, 256: 70.0}[n]
+        out.append(sim.make_workload(n, None, r, 0.5 / r, corners, 1e7, 520 + k, h=h, w=w))
+    return out
+
+
+@pytest.mark.parametrize("variant", [4, 5, 6])
+def test_spiral_batches_equal_individual_sweeps(variant):
+    """Stepped launches over spiral scans with batches of one to nine
+    positions (the default and the eight-slot inverse tiles): each scan gets
+    the bytes of its own sweeps."""
+    from paper_2308_10674_amd import sweep_multi
+    from paper_2308_10674_amd.engine import colour
+    scans = _spiral_scans()
+    sizes = set()
+    for wl in scans:
+        col, _ = colour(wl.positions, wl.n)
+        sizes |= set(np.bincount(col).tolist())
+    assert {1, 8, 9} <= sizes     # the eight-slot tile in one and in two slot rounds
+    together = [engine_for(wl) for wl in scans]
+    together[0].multi_variant = variant
+    err_m = sweep_multi(together, 2, errors=True)
+    for k, (wl, e_tog) in enumerate(zip(scans, together)):
+        e_alone = engine_for(wl)
+        err_a = e_alone.sweep(2, errors=True)
+        np.testing.assert_array_equal(e_tog.get_object(), e_alone.get_object(), err_msg=f"scan {k}")
+        np.testing.assert_array_equal(e_tog.get_probe(), e_alone.get_probe(), err_msg=f"scan {k}")
+        np.testing.assert_allclose(err_m[k], err_a, rtol=1e-13)
+
+
 def test_multi_graph_form_replays():
     """The persistent multi-scan launch captured as a graph, replayed by
     three calls in a row (the second and third reuse the graph): the same
