@@ -417,9 +417,12 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 // object step alpha conj(P) Delta / max|P|^2, probe increment
 // conj(S_j O) Delta / max|S_j O|^2 summed over slots in slot order, then
 // P_{b+1} written for the block.  bsize == 0 only refreshes the block's
-// max |P|^2.
+// max |P|^2.  lds: S R lines of Lds<N>::LINE (a line holds its slot row's
+// transform, then that row's probe increments, which the slot sum reads),
+// then the block's R probe rows (R N), read by every slot's threads instead
+// of a register copy per slot.
 template <int N, int R, int S, bool COH = false>
-__device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds, cf* dl) {
+__device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds) {
     using g = InvG<N, R, S>;
     const int t = threadIdx.x % g::T;
     const int rl = (threadIdx.x / g::T) % g::R;
@@ -429,18 +432,18 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     // e = k NT + threadIdx.x of the block's R rows (if e < R N)
     constexpr int OWN = g::OWN;
     cf p_own[OWN], acc[OWN];
+    cf* const pl = lds + g::S * g::R * Lds<N>::LINE;   // the block's probe rows
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
         const int e = k * g::NT + (int)threadIdx.x;
         const size_t own = (size_t)rb * g::R * N + e;
         p_own[k] = e < g::R * N ? ldc<COH>(&a.probe[own]) : cf{0.f, 0.f};
+        if (e < g::R * N) pl[e] = p_own[k];
         acc[k] = cf{0.f, 0.f};
     }
     if (a.bsize > 0) {
-        const cf* prow = a.probe + (size_t)r * N;
-        cf p[g::N1];
-#pragma unroll
-        for (int n1 = 0; n1 < g::N1; ++n1) p[n1] = ldc<COH>(&prow[g::N2 * n1 + t]);
+        __syncthreads();
+        const cf* prl = pl + rl * N;
         // every wave reduces all partial maxima itself (no barrier)
         float pm = 0.f;
 #pragma unroll
@@ -455,7 +458,6 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         cf wb[g::N1];
         twiddles_binv<N, +1>(wb, t, a.tw);
         cf* z = lds + (sl * g::R + rl) * Lds<N>::LINE;
-        cf* drow = dl + (sl * g::R + rl) * N;
         for (int g0 = 0; g0 < a.bsize; g0 += g::S) {
             const int slot = g0 + sl;
             const bool act = slot < a.bsize;
@@ -501,13 +503,15 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
             if (act) om = wm;
             constexpr float inv = 1.0f / (float)(N * N);
             const float pstep = 1.f / om;
+            line_sync();   // the increments overwrite what the line's lanes just read
             if (act) {
 #pragma unroll
                 for (int n1 = 0; n1 < g::N1; ++n1) {
                     const int col = g::N2 * n1 + t;
-                    const cf delta = inv * v[n1] - cmul(p[n1], o[n1]);
-                    store_through(&orow[col], axpy(ostep, cmulc(p[n1], delta), o[n1]));
-                    drow[col] = pstep * cmulc(o[n1], delta);
+                    const cf pv = prl[col];
+                    const cf delta = inv * v[n1] - cmul(pv, o[n1]);
+                    store_through(&orow[col], axpy(ostep, cmulc(pv, delta), o[n1]));
+                    z[col] = pstep * cmulc(o[n1], delta);
                 }
             }
             __syncthreads();
@@ -518,16 +522,17 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 const int e = k * g::NT + (int)threadIdx.x;
                 if (e >= g::R * N) continue;
                 // the same sequential sum, with eight loads in flight at a time
-                const cf* col = dl + e;
+                const cf* col = lds + (e / N) * Lds<N>::LINE + e % N;
+                constexpr int kSlotStride = g::R * Lds<N>::LINE;
                 int q = 0;
                 for (; q + 8 <= nact; q += 8) {
                     cf tq[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) tq[u] = col[(size_t)(q + u) * g::R * N];
+                    for (int u = 0; u < 8; ++u) tq[u] = col[(q + u) * kSlotStride];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) acc[k] = acc[k] + tq[u];
                 }
-                for (; q < nact; ++q) acc[k] = acc[k] + col[(size_t)q * g::R * N];
+                for (; q < nact; ++q) acc[k] = acc[k] + col[q * kSlotStride];
             }
             __syncthreads();
         }
@@ -593,9 +598,8 @@ __global__ __launch_bounds__((ColG<N, CB>::NT)) void k_cols(BatchArgs a) {
 template <int N, int R = ITile<N>::R, int S = ITile<N>::S, bool DEV = false>
 __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     using g = InvG<N, R, S>;
-    __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
-    __shared__ cf dl[g::S * g::R * N];
-    stage_rows_inv<N, g::R, g::S>(DEV ? resolved(a) : a, blockIdx.x, lds, dl);
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE + g::R * N];
+    stage_rows_inv<N, g::R, g::S>(DEV ? resolved(a) : a, blockIdx.x, lds);
 }
 
 // Several reconstructions at once: workgroup b belongs to descriptor i with
@@ -639,11 +643,10 @@ __global__ __launch_bounds__(kColNT<N>) void k_cols_multi(MultiArgs m) {
 template <int N>
 __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
     using g = InvG<N>;
-    __shared__ cf lds[g::S * g::R * Lds<N>::LINE];
-    __shared__ cf dl[g::S * g::R * N];
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE + g::R * N];
     const int i = (int)blockIdx.x / g::GI;
     const BatchArgs a = m.tab[i];
-    stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds, dl);
+    stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds);
 }
 
 // Mixed pattern sizes in one launch per stage.  Every size in {64, 128,
@@ -668,13 +671,12 @@ template <> struct MixTile<128> { static constexpr int RF = 4, RB = 16, R = 1, S
 template <> struct MixTile<256> { static constexpr int RF = 4, RB = 16, R = 1, S = 32, R2 = 4, S2 = 8; };
 template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
 template <int N> constexpr int kMixFwdLds = MixTile<N>::RF * Lds<N>::LINE;
-template <int N> constexpr int kMixInvLds = MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE;
-template <int N> constexpr int kMixInvDl = MixTile<N>::S * MixTile<N>::R * N;
+template <int N> constexpr int kMixInvLds =
+    MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE + (MixTile<N>::R > MixTile<N>::R2 ? MixTile<N>::R : MixTile<N>::R2) * N;
 constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 constexpr int kMixRowLdsMax = cmax3(kMixRowLds<64>, kMixRowLds<128>, kMixRowLds<256>);
 constexpr int kMixFwdLdsMax = cmax3(kMixFwdLds<64>, kMixFwdLds<128>, kMixFwdLds<256>);
 constexpr int kMixInvLdsMax = cmax3(kMixInvLds<64>, kMixInvLds<128>, kMixInvLds<256>);
-constexpr int kMixInvDlMax = cmax3(kMixInvDl<64>, kMixInvDl<128>, kMixInvDl<256>);
 
 template <int N>
 __device__ __forceinline__ void mix_rows_fwd(const BatchArgs& a, int local, cf* lds) {
@@ -691,15 +693,15 @@ __device__ __forceinline__ void mix_cols(const BatchArgs& a, int local, cf* lds,
 }
 
 template <int N>
-__device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* lds, cf* dl) {
+__device__ __forceinline__ void mix_rows_inv(const BatchArgs& a, int local, cf* lds) {
     using g = InvG<N, MixTile<N>::R, MixTile<N>::S>;
     using g2 = InvG<N, MixTile<N>::R2, MixTile<N>::S2>;
     static_assert(g::NT == kMixInvNT && g2::NT == kMixInvNT, "mixed inverse tile");
     static_assert(g2::S * g2::R <= g::S * g::R, "the small-batch tile fits the LDS of the default one");
     if (a.itile)
-        stage_rows_inv<N, g2::R, g2::S>(a, local, lds, dl);
+        stage_rows_inv<N, g2::R, g2::S>(a, local, lds);
     else
-        stage_rows_inv<N, g::R, g::S>(a, local, lds, dl);
+        stage_rows_inv<N, g::R, g::S>(a, local, lds);
 }
 
 __global__ __launch_bounds__(kMixFwdNT) void k_rows_fwd_mix(MultiArgs m) {
@@ -729,14 +731,13 @@ __global__ __launch_bounds__(kMixRowNT) void k_cols_mix(MultiArgs m) {
 
 __global__ __launch_bounds__(kMixInvNT) void k_rows_inv_mix(MultiArgs m) {
     __shared__ cf lds[kMixInvLdsMax];
-    __shared__ cf dl[kMixInvDlMax];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
     switch (a.n) {
-        case 64: mix_rows_inv<64>(a, local, lds, dl); break;
-        case 128: mix_rows_inv<128>(a, local, lds, dl); break;
-        case 256: mix_rows_inv<256>(a, local, lds, dl); break;
+        case 64: mix_rows_inv<64>(a, local, lds); break;
+        case 128: mix_rows_inv<128>(a, local, lds); break;
+        case 256: mix_rows_inv<256>(a, local, lds); break;
     }
 }
 
@@ -990,7 +991,7 @@ __device__ inline void sweep_error(const double* err_part, int64_t n_part, const
 // every non-empty batch.  ERR: the workgroup with local index 0 reduces
 // each sweep's error after its last batch (256 threads).
 template <int N, int RB, int CB, int IR, int IS, bool ERR>
-__device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds, cf* dl, double* red,
+__device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds, double* red,
                              int* ok_sh) {
     using rg = RowG<N, RB>;
     using cg = ColG<N, CB>;
@@ -1015,7 +1016,7 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
                 stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds, red);
             target += groups;
             if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
-            for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, true>(a, it, lds, dl);
+            for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, true>(a, it, lds);
             target += groups;
             if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
             // the maxima just written are those of the next batch's probe
@@ -1041,13 +1042,12 @@ __global__ __launch_bounds__(kSweepNT<N>) void k_sweep(ScanArgs sc, int* fault) 
     using ig = InvG<N, PTile<N>::R, PTile<N>::S>;
     static_assert(rg::NT == cg::NT && rg::NT == ig::NT, "one workgroup size for every stage");
     constexpr int NT = rg::NT;
-    constexpr int LINES = TB > ig::S * ig::R ? TB : ig::S * ig::R;
+    constexpr int LINES = TB > ig::S * ig::R + ig::R ? TB : ig::S * ig::R + ig::R;
     __shared__ cf lds[LINES * Lds<N>::LINE];
-    __shared__ cf dl[ig::S * ig::R * N];
     __shared__ double redd[NT / kWave];
     __shared__ int ok_sh;
     sc.gn = (int)gridDim.x;
-    persist_scan<N, TB, TB, ig::R, ig::S, false>(sc, (int)blockIdx.x, fault, lds, dl, redd, &ok_sh);
+    persist_scan<N, TB, TB, ig::R, ig::S, false>(sc, (int)blockIdx.x, fault, lds, redd, &ok_sh);
 }
 
 // Several independent scans in one launch (pattern sizes 64, 128, 256):
@@ -1063,26 +1063,24 @@ template <> struct MPTile<64>  { static constexpr int RB = 32, CB = 32, R0 = 4, 
 template <> struct MPTile<128> { static constexpr int RB = 16, CB = 16, R0 = 1, S0 = 16, R1 = 2, S1 = 8; };
 template <> struct MPTile<256> { static constexpr int RB = 16, CB = 16, R0 = 1, S0 = 16, R1 = 1, S1 = 16; };
 template <int N> constexpr int kMPLines =
-    cmax3(MPTile<N>::RB, MPTile<N>::S0 * MPTile<N>::R0, MPTile<N>::S1 * MPTile<N>::R1) * Lds<N>::LINE;
-template <int N> constexpr int kMPDl = cmax3(MPTile<N>::S0 * MPTile<N>::R0, MPTile<N>::S1 * MPTile<N>::R1, 0) * N;
+    cmax3(MPTile<N>::RB, MPTile<N>::S0 * MPTile<N>::R0 + MPTile<N>::R0, MPTile<N>::S1 * MPTile<N>::R1 + MPTile<N>::R1) *
+    Lds<N>::LINE;
 constexpr int kMPLds = cmax3(kMPLines<64>, kMPLines<128>, kMPLines<256>);
-constexpr int kMPDlMax = cmax3(kMPDl<64>, kMPDl<128>, kMPDl<256>);
 
 template <int N>
-__device__ __forceinline__ void multi_scan(const ScanArgs& sc, int local, int* fault, cf* lds, cf* dl, double* red,
+__device__ __forceinline__ void multi_scan(const ScanArgs& sc, int local, int* fault, cf* lds, double* red,
                                            int* ok_sh) {
     using t = MPTile<N>;
     static_assert(RowG<N, t::RB>::NT == kMP && ColG<N, t::CB>::NT == kMP, "multi-scan row and column tiles");
     static_assert(InvG<N, t::R0, t::S0>::NT == kMP && InvG<N, t::R1, t::S1>::NT == kMP, "multi-scan inverse tiles");
     if (sc.inv_tile == 0)
-        persist_scan<N, t::RB, t::CB, t::R0, t::S0, true>(sc, local, fault, lds, dl, red, ok_sh);
+        persist_scan<N, t::RB, t::CB, t::R0, t::S0, true>(sc, local, fault, lds, red, ok_sh);
     else
-        persist_scan<N, t::RB, t::CB, t::R1, t::S1, true>(sc, local, fault, lds, dl, red, ok_sh);
+        persist_scan<N, t::RB, t::CB, t::R1, t::S1, true>(sc, local, fault, lds, red, ok_sh);
 }
 
 __global__ __launch_bounds__(kMP) void k_multi_persist(const ScanArgs* scans, int count, int* fault) {
     __shared__ cf lds[kMPLds];
-    __shared__ cf dl[kMPDlMax];
     __shared__ double red[kMP / kWave];
     __shared__ int ok_sh;
     int i = 0;
@@ -1091,9 +1089,9 @@ __global__ __launch_bounds__(kMP) void k_multi_persist(const ScanArgs* scans, in
     const int local = (int)blockIdx.x - sc.g0;
     if (local < 0 || local >= sc.gn) return;
     switch (sc.a.n) {
-        case 64: multi_scan<64>(sc, local, fault, lds, dl, red, &ok_sh); break;
-        case 128: multi_scan<128>(sc, local, fault, lds, dl, red, &ok_sh); break;
-        case 256: multi_scan<256>(sc, local, fault, lds, dl, red, &ok_sh); break;
+        case 64: multi_scan<64>(sc, local, fault, lds, red, &ok_sh); break;
+        case 128: multi_scan<128>(sc, local, fault, lds, red, &ok_sh); break;
+        case 256: multi_scan<256>(sc, local, fault, lds, red, &ok_sh); break;
     }
 }
 
