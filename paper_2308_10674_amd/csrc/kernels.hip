@@ -420,7 +420,9 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 // max |P|^2.  lds: S R lines of Lds<N>::LINE (a line holds its slot row's
 // transform, then that row's probe increments, which the slot sum reads),
 // then the block's R probe rows (R N), read by every slot's threads instead
-// of a register copy per slot.
+// of a register copy per slot, then the twiddle table (N) that the slots'
+// inverse passes read (one load of it per workgroup instead of one set per
+// thread).
 template <int N, int R, int S, bool COH = false>
 __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* lds) {
     using g = InvG<N, R, S>;
@@ -433,6 +435,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
     constexpr int OWN = g::OWN;
     cf p_own[OWN], acc[OWN];
     cf* const pl = lds + g::S * g::R * Lds<N>::LINE;   // the block's probe rows
+    cf* const twl = pl + g::R * N;                     // the twiddle table
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
         const int e = k * g::NT + (int)threadIdx.x;
@@ -441,6 +444,7 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         if (e < g::R * N) pl[e] = p_own[k];
         acc[k] = cf{0.f, 0.f};
     }
+    for (int e = (int)threadIdx.x; e < N; e += g::NT) twl[e] = a.tw[e];
     if (a.bsize > 0) {
         __syncthreads();
         const cf* prl = pl + rl * N;
@@ -453,10 +457,6 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
         }
         pm = wave_max(pm);
         const float ostep = a.alpha / pm;
-        // twiddles ahead of the slot loads: the transform then waits for
-        // them and the spectrum row only (loads complete in issue order)
-        cf wb[g::N1];
-        twiddles_binv<N, +1>(wb, t, a.tw);
         cf* z = lds + (sl * g::R + rl) * Lds<N>::LINE;
         for (int g0 = 0; g0 < a.bsize; g0 += g::S) {
             const int slot = g0 + sl;
@@ -493,7 +493,11 @@ __device__ __forceinline__ void stage_rows_inv(const BatchArgs& a, int rb, cf* l
                 const int i = k * GT + (int)(threadIdx.x % GT);
                 wpart[k] = i < kWinParts<N> ? ldc<COH>(&a.winmax[ws * kWinParts<N> + i]) : 0.f;
             }
-            passBinv_to_lds<N, +1, 1>(v, z, t, wb);
+            {
+                cf wb[g::N1];
+                twiddles_binv<N, +1>(wb, t, twl);
+                passBinv_to_lds<N, +1, 1>(v, z, t, wb);
+            }
             line_sync();   // the line's threads are consecutive lanes of one wave
             passAinv_from_lds<N, +1>(v, z, t);
             float wm = 0.f;
@@ -598,7 +602,7 @@ __global__ __launch_bounds__((ColG<N, CB>::NT)) void k_cols(BatchArgs a) {
 template <int N, int R = ITile<N>::R, int S = ITile<N>::S, bool DEV = false>
 __global__ __launch_bounds__((InvG<N, R, S>::NT)) void k_rows_inv(BatchArgs a) {
     using g = InvG<N, R, S>;
-    __shared__ cf lds[g::S * g::R * Lds<N>::LINE + g::R * N];
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE + g::R * N + N];
     stage_rows_inv<N, g::R, g::S>(DEV ? resolved(a) : a, blockIdx.x, lds);
 }
 
@@ -643,7 +647,7 @@ __global__ __launch_bounds__(kColNT<N>) void k_cols_multi(MultiArgs m) {
 template <int N>
 __global__ __launch_bounds__((InvG<N>::NT)) void k_rows_inv_multi(MultiArgs m) {
     using g = InvG<N>;
-    __shared__ cf lds[g::S * g::R * Lds<N>::LINE + g::R * N];
+    __shared__ cf lds[g::S * g::R * Lds<N>::LINE + g::R * N + N];
     const int i = (int)blockIdx.x / g::GI;
     const BatchArgs a = m.tab[i];
     stage_rows_inv<N, g::R, g::S>(a, (int)blockIdx.x % g::GI, lds);
@@ -672,7 +676,7 @@ template <> struct MixTile<256> { static constexpr int RF = 4, RB = 16, R = 1, S
 template <int N> constexpr int kMixRowLds = MixTile<N>::RB * Lds<N>::LINE;
 template <int N> constexpr int kMixFwdLds = MixTile<N>::RF * Lds<N>::LINE;
 template <int N> constexpr int kMixInvLds =
-    MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE + (MixTile<N>::R > MixTile<N>::R2 ? MixTile<N>::R : MixTile<N>::R2) * N;
+    MixTile<N>::S * MixTile<N>::R * Lds<N>::LINE + (MixTile<N>::R > MixTile<N>::R2 ? MixTile<N>::R : MixTile<N>::R2) * N + N;
 constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 constexpr int kMixRowLdsMax = cmax3(kMixRowLds<64>, kMixRowLds<128>, kMixRowLds<256>);
 constexpr int kMixFwdLdsMax = cmax3(kMixFwdLds<64>, kMixFwdLds<128>, kMixFwdLds<256>);
@@ -1042,7 +1046,7 @@ __global__ __launch_bounds__(kSweepNT<N>) void k_sweep(ScanArgs sc, int* fault) 
     using ig = InvG<N, PTile<N>::R, PTile<N>::S>;
     static_assert(rg::NT == cg::NT && rg::NT == ig::NT, "one workgroup size for every stage");
     constexpr int NT = rg::NT;
-    constexpr int LINES = TB > ig::S * ig::R + ig::R ? TB : ig::S * ig::R + ig::R;
+    constexpr int LINES = TB > ig::S * ig::R + ig::R + 1 ? TB : ig::S * ig::R + ig::R + 1;
     __shared__ cf lds[LINES * Lds<N>::LINE];
     __shared__ double redd[NT / kWave];
     __shared__ int ok_sh;
@@ -1063,7 +1067,7 @@ template <> struct MPTile<64>  { static constexpr int RB = 32, CB = 32, R0 = 4, 
 template <> struct MPTile<128> { static constexpr int RB = 16, CB = 16, R0 = 1, S0 = 16, R1 = 2, S1 = 8; };
 template <> struct MPTile<256> { static constexpr int RB = 16, CB = 16, R0 = 1, S0 = 16, R1 = 1, S1 = 16; };
 template <int N> constexpr int kMPLines =
-    cmax3(MPTile<N>::RB, MPTile<N>::S0 * MPTile<N>::R0 + MPTile<N>::R0, MPTile<N>::S1 * MPTile<N>::R1 + MPTile<N>::R1) *
+    cmax3(MPTile<N>::RB, MPTile<N>::S0 * MPTile<N>::R0 + MPTile<N>::R0 + 1, MPTile<N>::S1 * MPTile<N>::R1 + MPTile<N>::R1 + 1) *
     Lds<N>::LINE;
 constexpr int kMPLds = cmax3(kMPLines<64>, kMPLines<128>, kMPLines<256>);
 
