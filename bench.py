@@ -287,25 +287,35 @@ def run_live(wl, tile=None):
             "note": "wall time including add_positions of each increment; error_after from one more sweep"}
 
 
-def roofline_of(r):
-    """Roofline entry of the dominant kernel (largest summed event time)."""
-    n = r["wl"].n
-    name, (ms, launches, units) = max(r["kernels"].items(), key=lambda kv: kv[1][0])
+def _kernel_roofline(name, n, ms, launches, units):
+    """Algorithmic bytes per launch of one kernel over its average duration."""
     per_launch_bytes = KERNEL_BYTES[name](n) * units / launches
     avg_s = ms / 1e3 / launches
     achieved = per_launch_bytes / avg_s / 1e9
     tr = load_traffic(name, n)
     return {
-        "bound": "hbm", "kernel": f"{name}<{n}>", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "kernel": f"{name}<{n}>", "achieved": round(achieved, 2), "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": None if tr is None else int(tr["bytes_per_launch"]),
         "traffic_GBps": None if tr is None else round(tr["bytes_per_launch"] / avg_s / 1e9, 2),
         "algorithmic_bytes_per_launch": round(per_launch_bytes),
         "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
-        "timing": "HIP events bound to each launch of the kernel (hipExtLaunchKernel) on its stream, "
-                  "summed over one run of the timed number of sweeps",
-        "kernel_times_ms": {k: round(v[0], 3) for k, v in r["kernels"].items()},
     }
+
+
+def roofline_of(r):
+    """Roofline entry of the dominant kernel (largest summed event time), and
+    the same figures for every stage of the path ("stages"): at 128 px the
+    column and inverse stages take nearly the same time, so either can be
+    the dominant one in a given run."""
+    n = r["wl"].n
+    name, (ms, launches, units) = max(r["kernels"].items(), key=lambda kv: kv[1][0])
+    out = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    out.update(_kernel_roofline(name, n, ms, launches, units))
+    out["timing"] = ("HIP events bound to each launch of the kernel (hipExtLaunchKernel) on its stream, "
+                     "summed over one run of the timed number of sweeps")
+    out["kernel_times_ms"] = {k: round(v[0], 3) for k, v in r["kernels"].items()}
+    out["stages"] = [_kernel_roofline(k, n, *v) for k, v in r["kernels"].items()]
+    return out
 
 
 def copy_bandwidth(reps=5):

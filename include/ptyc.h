@@ -194,7 +194,8 @@ int ptyc_sweep(ptyc_ctx* ctx, int32_t n_sweeps, const int64_t* order,
  * add_positions.  The orders are copied from pageable host memory, one
  * sweep at a time, and the call synchronises the stream before it returns.
  * Work memory needed: about 16 B per position of a sweep, 8 N^2 B per
- * position of the largest batch, 8 B per error partial and 8 B per sweep;
+ * position of the largest batch, 8 B per error partial (1, 4, 8, 32 and 64
+ * per position at 16, 32, 64, 128 and 256 px) and 8 B per sweep;
  * PTYC_ERR_ARG (nothing run) if that exceeds PTYC_NOALLOC_BYTES.  All calls
  * on one GPU share that array, whose contents are left from the last call:
  * calls that overlap in time on one GPU (other threads, other streams)

@@ -247,6 +247,9 @@ template <int N, int R_ = ITile<N>::R, int S_ = ITile<N>::S> struct InvG {
 // kProbeParts entries of max |P|^2 (N / R workgroups of R N / 64 owner
 // waves, whatever R); both counts are the same in every launch form.
 template <int N> constexpr int kWinParts = N * Fact<N>::N2 / kWave;
+// The column stage leaves its error sum as per-wave partials too: kColParts
+// entries per position (N / CB workgroups of CB N2 / 64 waves, whatever CB).
+template <int N> constexpr int kColParts = N * Fact<N>::N2 / kWave;
 template <int N> constexpr int kProbeParts = N * N / kWave;
 
 // Stores of the bulk data that the next kernel reads on other XCDs (the
@@ -347,8 +350,7 @@ __device__ __forceinline__ void stage_rows_fwd(const BatchArgs& a, int slot, int
 // Columns cb*CB .. of slot `slot`: 1D FFT, Psi' = sqrt(I_j) sgn(Psi) with
 // the error partial, inverse 1D FFT (unscaled), back to scratch.
 template <int N, int CB, int MODE = kModeEpie, bool COH = false>
-__device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds,
-                                           double* red) {
+__device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb, cf* lds) {
     using g = ColG<N, CB>;
     const int cl = threadIdx.x % CB, t = threadIdx.x / CB;
     // twiddles first: the first pass then waits for them and the spectrum
@@ -407,8 +409,11 @@ __device__ __forceinline__ void stage_cols(const BatchArgs& a, int slot, int cb,
 #pragma unroll
         for (int n1 = 0; n1 < g::N1; ++n1) store_through(&base[(size_t)(g::N2 * n1 + t) * N], v[n1]);
     }
-    const double tot = block_sum<g::NT>((double)e, red);
-    if (threadIdx.x == 0) stc<COH>(&a.err_part[(a.off + slot) * g::GC + cb], tot);
+    // one partial per wave (no workgroup barrier at the end of the stage)
+    static_assert((g::NT % kWave) == 0 && g::GC * (g::NT / kWave) == kColParts<N>, "error partials");
+    const double tot = wave_sum((double)e);
+    if (threadIdx.x % kWave == 0)
+        stc<COH>(&a.err_part[(a.off + slot) * kColParts<N> + cb * (g::NT / kWave) + threadIdx.x / kWave], tot);
 }
 
 // ---------------------------------------------------------------- stage 3
@@ -592,11 +597,10 @@ template <int N, int CB = Tile<N>::CB, bool DEV = false>
 __global__ __launch_bounds__((ColG<N, CB>::NT)) void k_cols(BatchArgs a) {
     using g = ColG<N, CB>;
     __shared__ cf lds[CB * Lds<N>::LINE];
-    __shared__ double red[g::NT / kWave];
     const BatchArgs b = DEV ? resolved(a) : a;
     const int slot = blockIdx.x / g::GC;
     if (DEV && slot >= b.bsize) return;
-    stage_cols<N, CB>(b, slot, blockIdx.x % g::GC, lds, red);
+    stage_cols<N, CB>(b, slot, blockIdx.x % g::GC, lds);
 }
 
 template <int N, int R = ITile<N>::R, int S = ITile<N>::S, bool DEV = false>
@@ -637,11 +641,10 @@ __global__ __launch_bounds__(kColNT<N>) void k_cols_multi(MultiArgs m) {
     constexpr int CB = Tile<N>::CB;
     using g = ColG<N, CB>;
     __shared__ cf lds[CB * Lds<N>::LINE];
-    __shared__ double red[g::NT / kWave];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
-    stage_cols<N, CB>(a, local / g::GC, local % g::GC, lds, red);
+    stage_cols<N, CB>(a, local / g::GC, local % g::GC, lds);
 }
 
 template <int N>
@@ -690,10 +693,10 @@ __device__ __forceinline__ void mix_rows_fwd(const BatchArgs& a, int local, cf* 
 }
 
 template <int N>
-__device__ __forceinline__ void mix_cols(const BatchArgs& a, int local, cf* lds, double* red) {
+__device__ __forceinline__ void mix_cols(const BatchArgs& a, int local, cf* lds) {
     using g = ColG<N, MixTile<N>::RB>;
     static_assert(g::NT == kMixRowNT, "mixed column tile");
-    stage_cols<N, MixTile<N>::RB>(a, local / g::GC, local % g::GC, lds, red);
+    stage_cols<N, MixTile<N>::RB>(a, local / g::GC, local % g::GC, lds);
 }
 
 template <int N>
@@ -722,14 +725,13 @@ __global__ __launch_bounds__(kMixFwdNT) void k_rows_fwd_mix(MultiArgs m) {
 
 __global__ __launch_bounds__(kMixRowNT) void k_cols_mix(MultiArgs m) {
     __shared__ cf lds[kMixRowLdsMax];
-    __shared__ double red[kMixRowNT / kWave];
     const int i = multi_find(m);
     const BatchArgs a = m.tab[i];
     const int local = (int)blockIdx.x - m.start[i];
     switch (a.n) {
-        case 64: mix_cols<64>(a, local, lds, red); break;
-        case 128: mix_cols<128>(a, local, lds, red); break;
-        case 256: mix_cols<256>(a, local, lds, red); break;
+        case 64: mix_cols<64>(a, local, lds); break;
+        case 128: mix_cols<128>(a, local, lds); break;
+        case 256: mix_cols<256>(a, local, lds); break;
     }
 }
 
@@ -770,8 +772,7 @@ __global__ __launch_bounds__(kColNT<N>) void k_cols_mode(BatchArgs a) {
     constexpr int CB = Tile<N>::CB;
     using g = ColG<N, CB>;
     __shared__ cf lds[CB * Lds<N>::LINE];
-    __shared__ double red[g::NT / kWave];
-    stage_cols<N, CB, MODE>(a, blockIdx.x / g::GC, blockIdx.x % g::GC, lds, red);
+    stage_cols<N, CB, MODE>(a, blockIdx.x / g::GC, blockIdx.x % g::GC, lds);
 }
 
 // ---------------------------------------------------------------- amplitude-loss adjoint
@@ -1017,7 +1018,7 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
             target += groups;
             if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
             for (int it = local; it < bs * cg::GC; it += sc.gn)
-                stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds, red);
+                stage_cols<N, CB, kModeEpie, true>(a, it / cg::GC, it % cg::GC, lds);
             target += groups;
             if (!group_barrier(sc.bar, local, sc.gn, target, sc.spin_limit, fault, ok_sh)) return;
             for (int it = local; it < ig::GI; it += sc.gn) stage_rows_inv<N, IR, IS, true>(a, it, lds);
@@ -1031,7 +1032,7 @@ __device__ void persist_scan(const ScanArgs& sc, int local, int* fault, cf* lds,
         if constexpr (ERR) {
             // the next sweep overwrites the partials only after its first
             // barrier, which this workgroup reaches after the reduction
-            if (sc.err && local == 0) sweep_error(a.err_part, sc.olen * cg::GC, a.order, sc.olen, sc.sum_i,
+            if (sc.err && local == 0) sweep_error(a.err_part, sc.olen * kColParts<N>, a.order, sc.olen, sc.sum_i,
                                                   sc.err + sw, red);
         }
     }
@@ -1382,12 +1383,12 @@ constexpr int mix_tile_r(int n, int itile) {
 }
 template <int N>
 Shape shape_n(int form, int variant) {
-    if (form == kFormPersistent) return Shape{kWinParts<N>, N / PTile<N>::B, kProbeParts<N>};
+    if (form == kFormPersistent) return Shape{kWinParts<N>, kColParts<N>, kProbeParts<N>};
     if constexpr (N >= 64) {
-        if (form == kFormMixed) return Shape{kWinParts<N>, N / MixTile<N>::RB, kProbeParts<N>};
+        if (form == kFormMixed) return Shape{kWinParts<N>, kColParts<N>, kProbeParts<N>};
     }
     if (variant < 0 || variant >= Variants<N>::K) variant = 0;
-    return Shape{kWinParts<N>, N / Variants<N>::v[variant].cb, kProbeParts<N>};
+    return Shape{kWinParts<N>, kColParts<N>, kProbeParts<N>};
 }
 
 template <int N, int V = 0>
@@ -1712,9 +1713,9 @@ int multi_need(int n, int max_batch, int inv_tile) {
 
 int multi_col_blocks(int n) {
     switch (n) {
-        case 64: return 64 / MPTile<64>::CB;
-        case 128: return 128 / MPTile<128>::CB;
-        case 256: return 256 / MPTile<256>::CB;
+        case 64: return kColParts<64>;
+        case 128: return kColParts<128>;
+        case 256: return kColParts<256>;
     }
     return 0;
 }

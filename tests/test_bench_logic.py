@@ -29,6 +29,12 @@ def test_roofline_of_the_dominant_kernel():
     assert rf["achieved"] == pytest.approx(per_launch / 10e-6 / 1e9, rel=1e-4)
     assert rf["frac"] == pytest.approx(rf["achieved"] / bench.HBM_PEAK_GBS, rel=1e-3)
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    # every stage is reported too, each against its own algorithmic bytes
+    st = {e["kernel"]: e for e in rf["stages"]}
+    assert set(st) == {"k_rows_fwd<128>", "k_cols<128>", "k_rows_inv<128>"}
+    assert st["k_cols<128>"]["algorithmic_bytes_per_launch"] == 4 * 128 * 128 * 30
+    assert st["k_cols<128>"]["avg_launch_us"] == pytest.approx(6.0)
+    assert st["k_rows_inv<128>"]["frac"] == rf["frac"]
 
 
 def test_traffic_lookup_needs_the_current_kernel_source(monkeypatch):
