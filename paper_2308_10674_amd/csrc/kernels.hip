@@ -154,8 +154,8 @@ template <> struct Tile<256> { static constexpr int RB = PTYC_RB256, CB = PTYC_C
 // Inverse row stage: R rows for S slots at a time (S*R*N2 threads); for the
 // probe step thread i < R*N owns element i of the block's R rows.  At 128 px
 // S = 40 holds the largest colour batches of a dense raster (36) in one
-// round; at 256 px the LDS allows at most 36 slots, which measured slower
-// than two rounds of 32.
+// round; at 256 px one round of 36 or 40 slots measured no faster than two
+// rounds of 32 for the few batches larger than 32.
 #ifndef PTYC_IR128
 #define PTYC_IR128 1
 #endif
